@@ -1,0 +1,169 @@
+"""CPU oracle for exact index-based SCAN — TEST INFRASTRUCTURE.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. It shares no code with the GPU library.
+The arithmetic lives in ``scan_oracle.cpp`` (plain C++17, no fast-math,
+``-ffp-contract=off``); this module only marshals numpy arrays.
+
+Parity status: every function here is pinned by the CPU tests
+(``tests/test_oracle_*.py``) against hand-worked graphs, closed forms,
+invariants and a brute-force direct SCAN written separately from the
+definitions of Section 3.1; none is "parity unpinned".
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "scan_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+COSINE = 0
+JACCARD = 1
+
+
+def build() -> str:
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-pthread", _SRC, "-o", _LIB_PATH + ".tmp"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.oracle_validate.argtypes = [i64, vp, vp, ctypes.POINTER(i64)]
+    lib.oracle_validate.restype = ctypes.c_int
+    lib.oracle_max_degree.argtypes = [i64, vp]
+    lib.oracle_max_degree.restype = i64
+    lib.oracle_similarities.argtypes = [i64, vp, vp, i32, i32, vp, vp]
+    lib.oracle_similarities.restype = None
+    lib.oracle_edge_similarity.argtypes = [vp, vp, i32, i64, i64, vp]
+    lib.oracle_edge_similarity.restype = f64
+    lib.oracle_neighbor_order.argtypes = [i64, vp, vp, vp, i32, vp, vp]
+    lib.oracle_neighbor_order.restype = None
+    lib.oracle_core_order.argtypes = [i64, vp, vp, i64, i32, vp, vp, vp]
+    lib.oracle_core_order.restype = None
+    lib.oracle_query.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, i32, f64, vp, vp]
+    lib.oracle_query.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data if a.size else None
+
+
+def _csr(g):
+    off = np.ascontiguousarray(g.off, dtype=np.int64)
+    adj = np.ascontiguousarray(g.adj, dtype=np.int32)
+    return off, adj
+
+
+@dataclass
+class OracleIndex:
+    n: int
+    off: np.ndarray      # int64[n+1]
+    dmax: int
+    kind: int
+    counts: np.ndarray   # int32[nnz], c = |N[u] ∩ N[v]| per CSR slot
+    sim: np.ndarray      # float64[nnz], per CSR slot
+    no_ids: np.ndarray   # int32[nnz]
+    no_sim: np.ndarray   # float64[nnz]
+    co_off: np.ndarray   # int64[dmax+3], indexed by mu
+    co_ids: np.ndarray   # int32[nnz]
+    co_thr: np.ndarray   # float64[nnz]
+
+
+def validate(g) -> int:
+    """-1 if g is a valid simple undirected CSR, else the first bad row."""
+    off, adj = _csr(g)
+    bad = ctypes.c_int64(-1)
+    rc = _load().oracle_validate(g.n, _p(off), _p(adj), ctypes.byref(bad))
+    return -1 if rc == 0 else int(bad.value)
+
+
+def similarities(g, kind: int = COSINE, threads: int = 1):
+    lib = _load()
+    off, adj = _csr(g)
+    nnz = int(off[-1])
+    counts = np.zeros(nnz, np.int32)
+    sim = np.zeros(nnz, np.float64)
+    lib.oracle_similarities(g.n, _p(off), _p(adj), kind, threads, _p(counts), _p(sim))
+    return counts, sim
+
+
+def edge_similarity(g, u: int, v: int, kind: int = COSINE):
+    """(c, sim) for one edge {u, v}."""
+    off, adj = _csr(g)
+    c = ctypes.c_int32()
+    s = _load().oracle_edge_similarity(_p(off), _p(adj), kind, u, v, ctypes.byref(c))
+    return int(c.value), float(s)
+
+
+def edge_similarities(g, us: np.ndarray, vs: np.ndarray, kind: int = COSINE):
+    off, adj = _csr(g)
+    lib = _load()
+    c = ctypes.c_int32()
+    cs = np.zeros(len(us), np.int32)
+    ss = np.zeros(len(us), np.float64)
+    po, pa = _p(off), _p(adj)
+    for i, (u, v) in enumerate(zip(us.tolist(), vs.tolist())):
+        ss[i] = lib.oracle_edge_similarity(po, pa, kind, u, v, ctypes.byref(c))
+        cs[i] = c.value
+    return cs, ss
+
+
+def neighbor_order(g, sim: np.ndarray, threads: int = 1):
+    off, adj = _csr(g)
+    nnz = int(off[-1])
+    no_ids = np.zeros(nnz, np.int32)
+    no_sim = np.zeros(nnz, np.float64)
+    _load().oracle_neighbor_order(g.n, _p(off), _p(adj), _p(np.ascontiguousarray(sim)), threads,
+                                  _p(no_ids), _p(no_sim))
+    return no_ids, no_sim
+
+
+def core_order(g, no_sim: np.ndarray, dmax: int, threads: int = 1):
+    off, _ = _csr(g)
+    nnz = int(off[-1])
+    co_off = np.zeros(dmax + 3, np.int64)
+    co_ids = np.zeros(nnz, np.int32)
+    co_thr = np.zeros(nnz, np.float64)
+    _load().oracle_core_order(g.n, _p(off), _p(np.ascontiguousarray(no_sim)), dmax, threads,
+                              _p(co_off), _p(co_ids), _p(co_thr))
+    return co_off, co_ids, co_thr
+
+
+def build_index(g, kind: int = COSINE, threads: int = 1) -> OracleIndex:
+    off, _ = _csr(g)
+    dmax = int(_load().oracle_max_degree(g.n, _p(off)))
+    counts, sim = similarities(g, kind, threads)
+    no_ids, no_sim = neighbor_order(g, sim, threads)
+    co_off, co_ids, co_thr = core_order(g, no_sim, dmax, threads)
+    return OracleIndex(g.n, off, dmax, kind, counts, sim, no_ids, no_sim, co_off, co_ids, co_thr)
+
+
+def query(ix: OracleIndex, mu: int, eps: float):
+    """(memberships int32[n], is_core uint8[n]) for (mu, eps)."""
+    memb = np.zeros(ix.n, np.int32)
+    core = np.zeros(ix.n, np.uint8)
+    rc = _load().oracle_query(ix.n, _p(ix.off), _p(ix.no_ids), _p(ix.no_sim), _p(ix.co_off),
+                              _p(ix.co_ids), _p(ix.co_thr), ix.dmax, int(mu), float(eps),
+                              _p(memb), _p(core))
+    if rc != 0:
+        raise ValueError(f"oracle_query rejected mu={mu} eps={eps}")
+    return memb, core

@@ -1,0 +1,284 @@
+// CPU oracle for exact index-based SCAN (Tseng, Dhulipala and Shun,
+// "Parallel Index-Based Structural Graph Clustering and Its Approximation",
+// SIGMOD 2021).
+//
+// TEST INFRASTRUCTURE, NOT PRODUCT CODE. Only the test suite, the smoke check
+// and the CPU-baseline leg of the benchmark may load this library. It shares
+// no code, header, table or helper with the GPU library; both sides read the
+// same CSR produced by the input generators and nothing else.
+//
+// Plain, slow and written for a reader checking it against the paper:
+//   * similarities: Section 3.1 (closed neighbourhoods) and Section 2.1.1
+//     (cosine / Jaccard), computed per undirected edge as in Algorithm 1;
+//   * neighbour order and core order: Section 3.2 and Algorithm 2;
+//   * query: Algorithms 3 (GetCores), 5 (Cluster) and 4 (AssignNonCores) with
+//     the deterministic border rule of Section 7.3.4 (most similar
+//     epsilon-similar core, ties to the lower vertex id).
+//
+// Readings where the paper leaves a choice (each also listed in the design
+// notes):
+//   * ids are 0-based; the graph is simple (no loops, no multi-edges) and
+//     stored with both directions, rows strictly ascending;
+//   * c = |N[u] ∩ N[v]| over closed neighbourhoods = |N(u) ∩ N(v)| + 2 and
+//     a(v) = |N[v]| = deg(v) + 1;
+//   * cosine  = c / sqrt((double)a_u * (double)a_v)   (one IEEE sqrt, one div);
+//     Jaccard = (double)c / (double)(a_u + a_v - c)  (one IEEE div);
+//   * the neighbour order stores open neighbourhoods; self would rank first
+//     with similarity 1, so the core threshold of v for mu is the (mu-1)-th
+//     largest neighbour similarity, i.e. no_sim[off[v] + mu - 2];
+//   * ties in both orders go to the lower vertex id; keys are the FP64 values;
+//   * the core order has segments mu = 2 .. Dmax+1, segment mu holding every v
+//     with deg(v) >= mu-1; co_off has Dmax+3 entries indexed by mu;
+//   * query: mu < 2 or NaN eps is rejected; mu > Dmax+1 gives no cores;
+//     clusters are labelled by their smallest core id, unclustered = -1.
+//
+// Compile without fast-math and with -ffp-contract=off.
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <vector>
+
+namespace {
+
+// Runs body(i) for i in [0, count) on `threads` std::threads in contiguous
+// chunks; threads <= 1 runs inline.
+template <class F>
+void parallel_for(int64_t count, int threads, F body) {
+  if (threads <= 1 || count < 2) {
+    for (int64_t i = 0; i < count; ++i) body(i);
+    return;
+  }
+  std::vector<std::thread> pool;
+  int64_t chunk = (count + threads - 1) / threads;
+  for (int t = 0; t < threads; ++t) {
+    int64_t lo = t * chunk, hi = std::min<int64_t>(count, lo + chunk);
+    if (lo >= hi) break;
+    pool.emplace_back([=]() {
+      for (int64_t i = lo; i < hi; ++i) body(i);
+    });
+  }
+  for (auto &th : pool) th.join();
+}
+
+// Same, but hands out items one at a time from a shared counter, for skewed
+// per-item costs.
+template <class F>
+void parallel_for_dynamic(int64_t count, int threads, F body) {
+  if (threads <= 1 || count < 2) {
+    for (int64_t i = 0; i < count; ++i) body(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&]() {
+      for (;;) {
+        int64_t i = next.fetch_add(64);
+        if (i >= count) break;
+        for (int64_t j = i; j < std::min<int64_t>(count, i + 64); ++j) body(j);
+      }
+    });
+  for (auto &th : pool) th.join();
+}
+
+inline int64_t degree(const int64_t *off, int64_t v) { return off[v + 1] - off[v]; }
+
+// |N(u) ∩ N(v)| by a two-pointer merge of the two sorted rows.
+int64_t common_open_neighbours(const int64_t *off, const int32_t *adj, int64_t u, int64_t v) {
+  int64_t i = off[u], ie = off[u + 1], j = off[v], je = off[v + 1], t = 0;
+  while (i < ie && j < je) {
+    if (adj[i] < adj[j]) ++i;
+    else if (adj[i] > adj[j]) ++j;
+    else { ++t; ++i; ++j; }
+  }
+  return t;
+}
+
+// Similarity of adjacent u, v from c = |N[u] ∩ N[v]| and the closed sizes.
+double similarity(int kind, int64_t c, int64_t a_u, int64_t a_v) {
+  if (kind == 0) return (double)c / std::sqrt((double)a_u * (double)a_v);
+  return (double)c / (double)(a_u + a_v - c);
+}
+
+// Sort key for both orders: similarity descending, then vertex id ascending.
+struct Entry {
+  double key;
+  int32_t id;
+};
+inline bool before(const Entry &x, const Entry &y) {
+  if (x.key != y.key) return x.key > y.key;
+  return x.id < y.id;
+}
+
+}  // namespace
+
+extern "C" {
+
+// 0 if (off, adj) is a simple undirected graph in CSR form with strictly
+// ascending rows (Section 2.2); -2 otherwise, with *bad_vertex set to the
+// first offending row.
+int oracle_validate(int64_t n, const int64_t *off, const int32_t *adj, int64_t *bad_vertex) {
+  *bad_vertex = -1;
+  if (n < 0 || off[0] != 0) return -2;
+  for (int64_t v = 0; v < n; ++v) {
+    if (off[v + 1] < off[v]) { *bad_vertex = v; return -2; }
+    for (int64_t s = off[v]; s < off[v + 1]; ++s) {
+      int64_t w = adj[s];
+      bool ok = w >= 0 && w < n && w != v && (s == off[v] || adj[s - 1] < w);
+      if (ok) ok = std::binary_search(adj + off[w], adj + off[w + 1], (int32_t)v);
+      if (!ok) { *bad_vertex = v; return -2; }
+    }
+  }
+  return 0;
+}
+
+int64_t oracle_max_degree(int64_t n, const int64_t *off) {
+  int64_t d = 0;
+  for (int64_t v = 0; v < n; ++v) d = std::max(d, degree(off, v));
+  return d;
+}
+
+// Algorithm 1 (unweighted): for every undirected edge {u, v}, u < v, count
+// the closed-neighbourhood intersection and store c and the similarity in both
+// CSR slots (u -> v and v -> u). counts may be null.
+void oracle_similarities(int64_t n, const int64_t *off, const int32_t *adj, int32_t kind,
+                         int32_t threads, int32_t *counts, double *sim) {
+  parallel_for_dynamic(n, threads, [&](int64_t u) {
+    for (int64_t s = off[u]; s < off[u + 1]; ++s) {
+      int64_t v = adj[s];
+      if (v < u) continue;
+      int64_t c = common_open_neighbours(off, adj, u, v) + 2;
+      double x = similarity(kind, c, degree(off, u) + 1, degree(off, v) + 1);
+      int64_t m = std::lower_bound(adj + off[v], adj + off[v + 1], (int32_t)u) - adj;
+      sim[s] = x;
+      sim[m] = x;
+      if (counts) {
+        counts[s] = (int32_t)c;
+        counts[m] = (int32_t)c;
+      }
+    }
+  });
+}
+
+// One edge, for sampled checks at sizes where the full pass is too slow.
+double oracle_edge_similarity(const int64_t *off, const int32_t *adj, int32_t kind, int64_t u,
+                              int64_t v, int32_t *count) {
+  int64_t c = common_open_neighbours(off, adj, u, v) + 2;
+  if (count) *count = (int32_t)c;
+  return similarity(kind, c, degree(off, u) + 1, degree(off, v) + 1);
+}
+
+// Algorithm 2, MakeNeighborOrder: each row sorted by non-increasing
+// similarity, ties by lower id.
+void oracle_neighbor_order(int64_t n, const int64_t *off, const int32_t *adj, const double *sim,
+                           int32_t threads, int32_t *no_ids, double *no_sim) {
+  parallel_for_dynamic(n, threads, [&](int64_t v) {
+    std::vector<Entry> row;
+    for (int64_t s = off[v]; s < off[v + 1]; ++s) row.push_back({sim[s], adj[s]});
+    std::stable_sort(row.begin(), row.end(), before);
+    for (size_t i = 0; i < row.size(); ++i) {
+      no_ids[off[v] + i] = row[i].id;
+      no_sim[off[v] + i] = row[i].key;
+    }
+  });
+}
+
+// Algorithm 2, MakeCoreOrder: for mu = 2 .. Dmax+1 the segment CO[mu] holds
+// every v with |N[v]| >= mu, sorted by non-increasing core threshold
+// no_sim[off[v] + mu - 2], ties by lower id. co_off has dmax + 3 entries.
+void oracle_core_order(int64_t n, const int64_t *off, const double *no_sim, int64_t dmax,
+                       int32_t threads, int64_t *co_off, int32_t *co_ids, double *co_thr) {
+  // seg[mu - 2] collects (threshold, v) for every v with deg(v) >= mu - 1,
+  // visiting v in ascending order.
+  std::vector<std::vector<Entry>> seg((size_t)std::max<int64_t>(dmax, 0));
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t j = 0; j < degree(off, v); ++j) seg[j].push_back({no_sim[off[v] + j], (int32_t)v});
+  co_off[0] = co_off[1] = co_off[2] = 0;
+  for (int64_t mu = 2; mu <= dmax + 1; ++mu) co_off[mu + 1] = co_off[mu] + (int64_t)seg[mu - 2].size();
+  parallel_for_dynamic(dmax, threads, [&](int64_t i) {
+    int64_t mu = i + 2;
+    std::stable_sort(seg[i].begin(), seg[i].end(), before);
+    for (size_t k = 0; k < seg[i].size(); ++k) {
+      co_ids[co_off[mu] + k] = seg[i][k].id;
+      co_thr[co_off[mu] + k] = seg[i][k].key;
+    }
+  });
+}
+
+// Algorithm 5 (Cluster) over the index, with Algorithm 3 (GetCores) and
+// Algorithm 4 (AssignNonCores) under the Section 7.3.4 border rule.
+// memberships[v] = smallest core id of v's cluster, or -1. is_core may be null.
+// Returns 0, or -1 for mu < 2 or NaN eps.
+int oracle_query(int64_t n, const int64_t *off, const int32_t *no_ids, const double *no_sim,
+                 const int64_t *co_off, const int32_t *co_ids, const double *co_thr, int64_t dmax,
+                 int32_t mu, double eps, int32_t *memberships, uint8_t *is_core) {
+  if (mu < 2 || std::isnan(eps)) return -1;
+  std::vector<uint8_t> core((size_t)n, 0);
+  std::vector<int32_t> cores;
+  // GetCores: the prefix of CO[mu] whose thresholds are >= eps.
+  if (mu <= dmax + 1) {
+    for (int64_t k = co_off[mu]; k < co_off[mu + 1] && co_thr[k] >= eps; ++k) {
+      cores.push_back(co_ids[k]);
+      core[co_ids[k]] = 1;
+    }
+  }
+  // similar_edges: the eps-prefix of NO[u] for each core u.
+  struct Sim {
+    int32_t u, w;
+    double s;
+  };
+  std::vector<Sim> similar;
+  for (int32_t u : cores)
+    for (int64_t k = off[u]; k < off[u + 1] && no_sim[k] >= eps; ++k)
+      similar.push_back({u, no_ids[k], no_sim[k]});
+  // Connected components of the cores under core-core similar edges (BFS);
+  // each component is labelled by its smallest member.
+  std::vector<std::vector<int32_t>> nbr((size_t)n);
+  for (const Sim &e : similar)
+    if (core[e.w]) {
+      nbr[e.u].push_back(e.w);
+      nbr[e.w].push_back(e.u);
+    }
+  std::vector<int32_t> label((size_t)n, -1);
+  std::vector<int32_t> sorted_cores = cores;
+  std::sort(sorted_cores.begin(), sorted_cores.end());
+  for (int32_t r : sorted_cores) {
+    if (label[r] != -1) continue;
+    std::deque<int32_t> q{r};
+    label[r] = r;  // r is the smallest unlabelled core, so it is the minimum of its component
+    while (!q.empty()) {
+      int32_t x = q.front();
+      q.pop_front();
+      for (int32_t y : nbr[x])
+        if (label[y] == -1) {
+          label[y] = r;
+          q.push_back(y);
+        }
+    }
+  }
+  // AssignNonCores: each non-core endpoint of a similar edge joins the cluster
+  // of its most similar core neighbour, ties to the lower core id.
+  std::vector<int32_t> best_core((size_t)n, -1);
+  std::vector<double> best_sim((size_t)n, 0.0);
+  for (const Sim &e : similar) {
+    if (core[e.w]) continue;
+    int32_t b = best_core[e.w];
+    if (b == -1 || e.s > best_sim[e.w] || (e.s == best_sim[e.w] && e.u < b)) {
+      best_core[e.w] = e.u;
+      best_sim[e.w] = e.s;
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    if (core[v]) memberships[v] = label[v];
+    else memberships[v] = best_core[v] == -1 ? -1 : label[best_core[v]];
+    if (is_core) is_core[v] = core[v];
+  }
+  return 0;
+}
+
+}  // extern "C"
