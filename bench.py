@@ -1,0 +1,204 @@
+"""Benchmark: exact cosine SCAN index build on R-MAT scale 20 (edge factor 16,
+(a,b,c,d) = (.57,.19,.19,.05), symmetrised, deduplicated, self-loops removed,
+int32 CSR) on one MI355X, plus (mu, eps) query latency one at a time vs
+batched on the same index.
+
+One step = one full index build (degrees, ownership plan, intersection +
+FP64 similarity, neighbour order, core order) from a CSR resident in HBM to
+the index resident in HBM. Prints ONE JSON line on stdout; progress goes to
+stderr.
+
+  python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--scale 20]
+                  [--no-cpu-baseline] [--queries 200]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def byte_model(st: dict, s_off: int) -> dict:
+    """Algorithmic bytes (fixed before measurement): CSR read once, W_min
+    shorter-row element reads plus one probe each (Algorithm 1's min-side
+    work), similarities written once per slot, neighbour-order and core-order
+    reads and writes."""
+    n, nnz, wmin = st["n"], st["nnz"], st["w_min"]
+    intersect = s_off * (n + 1) + 4 * nnz + 8 * wmin + 8 * nnz
+    build = s_off * (n + 1) + 56 * nnz + 8 * wmin
+    floor = s_off * (n + 1) + 28 * nnz
+    return {"intersect": intersect, "build": build, "floor": floor}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=20)
+    ap.add_argument("--queries", type=int, default=200)
+    ap.add_argument("--query-batch", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the index build and queries run on a single MI355X); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen
+    import paper_2012_11188_amd as scan
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
+    st = graphgen.degree_stats(g)
+    log(f"graph rmat{args.scale}: n={g.n} |E|={g.num_edges} nnz={g.nnz} dmax={st['dmax']} "
+        f"w_min={st['w_min']} ({time.time() - t0:.1f}s)")
+    off = torch.from_numpy(g.off.astype(np.int32)).cuda()
+    adj = torch.from_numpy(g.adj).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def one_build(profile=False):
+        return scan.scan_build_index(off, adj, scan.COSINE, scan.SCAN_PROFILE if profile else 0)
+
+    for i in range(args.warmup):
+        ix = one_build(True)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {scan.scan_index_build_profile(ix)}")
+        del ix
+
+    # Timed region: exactly `steps` builds.
+    profiles = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    keep = []
+    for _ in range(args.steps):
+        ix = one_build(True)
+        keep.append(ix)
+        if len(keep) > 1:
+            profiles.append(scan.scan_index_build_profile(keep.pop(0)))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    profiles.append(scan.scan_index_build_profile(keep[-1]))
+    dev_ms = ev0.elapsed_time(ev1)
+    ix = keep[-1]
+    ms_per_step = wall * 1000.0 / args.steps
+    edges = g.num_edges
+    value = edges * args.steps / wall
+    med = lambda key: float(np.median([p[key] for p in profiles]))
+    phases = {k: med(k) for k in ("total_ms", "prepare_ms", "plan_ms", "intersect_ms", "no_sort_ms",
+                                  "core_order_ms")}
+    log(f"build: {ms_per_step:.2f} ms/step wall, device span {dev_ms / args.steps:.2f} ms/step, phases {phases}")
+
+    bm = byte_model(st, 4)
+    int_ms = phases["intersect_ms"]
+    achieved = bm["intersect"] / (int_ms * 1e-3) / 1e9
+    build_gbs = bm["build"] / (phases["total_ms"] * 1e-3) / 1e9
+
+    # Queries: mu ~ U{2..16}, eps ~ U{0.10, 0.15, ..., 0.90}; one at a time
+    # (synchronous) vs batched.
+    rng = np.random.default_rng(7)
+    q_mu = rng.integers(2, 17, args.queries)
+    q_eps = np.array([(10 + 5 * k) / 100.0 for k in rng.integers(0, 17, args.queries)])
+    memb = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for i in range(5):
+        scan.scan_query(ix, int(q_mu[i]), float(q_eps[i]), memb)
+    torch.cuda.synchronize()
+    single = []
+    for mu, eps in zip(q_mu, q_eps):
+        t = time.perf_counter()
+        scan.scan_query(ix, int(mu), float(eps), memb)
+        torch.cuda.synchronize()
+        single.append((time.perf_counter() - t) * 1e3)
+    B = args.query_batch
+    out = torch.empty((B, g.n), dtype=torch.int32, device="cuda")
+    batched, tb0 = [], time.perf_counter()
+    for i in range(0, args.queries, B):
+        t = time.perf_counter()
+        scan.scan_query_batch(ix, q_mu[i:i + B], q_eps[i:i + B], out[: len(q_mu[i:i + B])])
+        torch.cuda.synchronize()
+        batched += [(time.perf_counter() - t) * 1e3] * len(q_mu[i:i + B])
+    tb = time.perf_counter() - tb0
+    ts = sum(single) / 1e3
+    query = {
+        "mu": "U{2..16}", "eps": "U{0.10,0.15,...,0.90}", "queries": args.queries, "batch": B,
+        "one_at_a_time": {"p50_ms": float(np.percentile(single, 50)), "p99_ms": float(np.percentile(single, 99)),
+                          "qps": args.queries / ts},
+        "batched": {"p50_ms": float(np.percentile(batched, 50)), "p99_ms": float(np.percentile(batched, 99)),
+                    "qps": args.queries / tb},
+    }
+    log(f"queries: {query}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline: oracle full build on {threads} threads ...")
+        t = time.perf_counter()
+        oracle.build_index(g, oracle.COSINE, threads=threads)
+        tc = time.perf_counter() - t
+        cpu = {"value": edges / tc, "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "sample": f"one full cosine index build of the same R-MAT-{args.scale} graph "
+                         f"(similarities, neighbour order, core order), {tc:.1f} s"}
+        log(f"cpu baseline: {tc:.1f} s")
+
+    rec = {
+        "metric": "index-build edges/s (R-MAT-20); query p50/p99 ms, batched vs one-at-a-time",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_cosine_index_build", "scale": args.scale,
+                   "edge_factor": args.edge_factor, "abcd": [0.57, 0.19, 0.19, 0.05], "seed": args.seed,
+                   "n": g.n, "edges": edges, "nnz": g.nnz, "dmax": st["dmax"], "w_min": st["w_min"],
+                   "offsets": "int32", "similarity": "cosine", "ids": "int32"},
+        "phases_ms": phases,
+        "device_ms_per_step": dev_ms / args.steps,
+        "query": query,
+        "roofline": {"bound": "hbm", "kernel": "k_intersect (all degree-class launches of one build)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bm["intersect"], "launch_ms": int_ms},
+        "build_roofline": {"bytes": bm["build"], "floor_bytes": bm["floor"], "achieved": build_gbs,
+                           "frac": build_gbs / HBM_PEAK_GBS,
+                           "floor_frac": bm["floor"] / (phases["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * scan.h — C ABI of an exact index-based SCAN library for AMD MI355X (gfx950).
+ *
+ * Method: Tseng, Dhulipala and Shun, "Parallel Index-Based Structural Graph
+ * Clustering and Its Approximation" (SIGMOD 2021):
+ *   - structural similarity over closed neighbourhoods (Section 3.1),
+ *     cosine or Jaccard (Section 2.1.1), computed per edge as in Algorithm 1;
+ *   - the GS*-style index: neighbour order NO and core order CO (Section 3.2,
+ *     Algorithm 2);
+ *   - (mu, eps) clustering queries over the index (Section 4.2, Algorithms
+ *     3-5), with the deterministic border rule of Section 7.3.4.
+ *
+ * Conventions shared by every entry point
+ *   - Vertex ids are 0-based int32. A graph is simple and undirected, stored as
+ *     CSR with both directions of every edge, each row strictly ascending, no
+ *     self-loops (Section 2.2). nnz = 2|E|.
+ *   - Similarities are IEEE binary64, computed exactly as
+ *       cosine : c / sqrt((double)a_u * (double)a_v)
+ *       Jaccard: (double)c / (double)(a_u + a_v - c)
+ *     with c = |N[u] ∩ N[v]| and a_v = |N[v]| = deg(v) + 1.
+ *   - Both orders sort by similarity descending, ties by vertex id ascending.
+ *   - Query results: memberships[v] is the smallest core id of v's cluster, or
+ *     -1 if v is unclustered. A border vertex joins the cluster of its most
+ *     similar eps-similar core neighbour, ties to the lower id.
+ *   - Errors: every call returns a scan_status; on failure scan_last_error()
+ *     returns a message for the calling thread. No C++ exception crosses the
+ *     ABI. Argument errors are detected before any device work is enqueued.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream). Device
+ *     work is enqueued on it asynchronously unless a function says otherwise.
+ *   - Ownership: the caller owns the CSR and every output buffer; the library
+ *     never keeps a caller pointer after a call returns. The library owns each
+ *     scan_index and scan_server and their device memory until the matching
+ *     free/destroy call.
+ */
+#ifndef SCAN_MI355X_H
+#define SCAN_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCAN_OK = 0,
+  SCAN_EINVAL = -1,  /* bad argument: null pointer, negative size, odd nnz,
+                        unknown kind, mu < 2, NaN eps, short buffer        */
+  SCAN_EGRAPH = -2,  /* (with SCAN_VALIDATE) not a simple undirected CSR   */
+  SCAN_ENOMEM = -3,  /* device allocation failed                           */
+  SCAN_EDEVICE = -4, /* HIP runtime error                                  */
+  SCAN_EBUSY = -5    /* server admission refused: no slot or memory        */
+} scan_status;
+
+typedef enum { SCAN_SIM_COSINE = 0, SCAN_SIM_JACCARD = 1 } scan_sim_kind;
+
+/* Build flags. */
+enum {
+  SCAN_VALIDATE = 1u,    /* check the CSR on the device; SCAN_EGRAPH if bad
+                            (synchronises the stream)                        */
+  SCAN_KEEP_SIMS = 2u,   /* keep per-CSR-slot similarities (export SIMS)      */
+  SCAN_KEEP_COUNTS = 4u, /* keep per-CSR-slot counts c (export COUNTS)        */
+  SCAN_PROFILE = 8u      /* record per-phase device times with hipEvents      */
+};
+
+/* Per-phase device times of a build made with SCAN_PROFILE, in milliseconds,
+ * from hipEvents recorded on the build stream between phases:
+ *   prepare     degrees, offsets, max degree (and validation if asked)
+ *   plan        edge ownership and chunk lists per table class
+ *   intersect   all intersection + similarity launches
+ *   no_sort     neighbour-order segmented sort
+ *   core_order  core-order sizes, placement and segmented sort
+ * total spans all of them (host synchronisation gaps included). */
+typedef struct {
+  double total_ms;
+  double prepare_ms;
+  double plan_ms;
+  double intersect_ms;
+  double no_sort_ms;
+  double core_order_ms;
+  int32_t intersect_launches;
+  int32_t owners;       /* vertices that own at least one edge */
+} scan_build_profile;
+
+/* A graph in CSR form. offsets has n+1 entries of offset_bits (32 or 64)
+ * bits; adj has nnz int32 entries. on_device = 1: both are device pointers
+ * (read during the build, not retained); 0: host pointers (copied to the
+ * device first). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  int32_t offset_bits;
+  int32_t on_device;
+  const void *offsets;
+  const int32_t *adj;
+} scan_csr;
+
+typedef struct scan_index scan_index; /* opaque, device resident, immutable */
+
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  int64_t dmax;          /* maximum degree; CO has segments mu = 2..dmax+1  */
+  int32_t kind;          /* scan_sim_kind                                   */
+  int32_t flags;         /* build flags kept (SCAN_KEEP_*)                  */
+  int64_t device_bytes;  /* device memory held by the index                 */
+} scan_index_info;
+
+/* Index arrays, all device resident, for scan_index_export / _device_ptr.
+ *   OFFSETS  int64[n+1]     CSR offsets, shared by NO and the slot arrays
+ *   NO_IDS   int32[nnz]     row v of NO = neighbours of v, sim desc / id asc
+ *   NO_SIM   double[nnz]    their similarities
+ *   CO_OFF   int64[dmax+3]  CO[mu] = co entries [CO_OFF[mu], CO_OFF[mu+1])
+ *   CO_IDS   int32[nnz]     vertices with deg >= mu-1, thr desc / id asc
+ *   CO_THR   double[nnz]    core thresholds NO_SIM[off[v] + mu - 2]
+ *   SIMS     double[nnz]    per CSR slot, same order as adj (SCAN_KEEP_SIMS)
+ *   COUNTS   int32[nnz]     c per CSR slot (SCAN_KEEP_COUNTS)               */
+typedef enum {
+  SCAN_ARR_OFFSETS = 0,
+  SCAN_ARR_NO_IDS = 1,
+  SCAN_ARR_NO_SIM = 2,
+  SCAN_ARR_CO_OFF = 3,
+  SCAN_ARR_CO_IDS = 4,
+  SCAN_ARR_CO_THR = 5,
+  SCAN_ARR_SIMS = 6,
+  SCAN_ARR_COUNTS = 7
+} scan_array;
+
+/* Device memory hooks. alloc returns a device pointer of at least `bytes`
+ * usable on `stream`, or NULL; release frees it (stream-ordered). Passing
+ * NULL for both restores hipMalloc/hipFree. Process-wide; set it before
+ * building. */
+typedef void *(*scan_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*scan_release_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+scan_status scan_set_allocator(scan_alloc_fn alloc, scan_release_fn release, void *ctx);
+
+/* Builds the index of Section 3.2 (Algorithms 1 and 2) for graph g.
+ * Enqueues degrees, per-edge intersection + similarity, the neighbour-order
+ * segmented sort and the core-order sort on `stream`; *out is usable on
+ * `stream` immediately (later work on other streams must wait for it).
+ * The CSR must stay valid until the stream reaches the end of the build.
+ * Errors: SCAN_EINVAL (null g/out/pointers with n > 0, n < 0, nnz < 0, odd
+ * nnz, offset_bits not 32/64, unknown kind or flag, n or nnz too large for
+ * int32 ids / the chosen offsets), SCAN_EGRAPH (SCAN_VALIDATE only),
+ * SCAN_ENOMEM, SCAN_EDEVICE. On error *out is NULL. */
+scan_status scan_build_index(const scan_csr *g, scan_sim_kind kind, uint32_t flags, void *stream,
+                             scan_index **out);
+
+/* Builds `count` independent indexes (one per graph) with the graphs' work
+ * merged into shared launches: one degree pass, one persistent intersection
+ * launch over all graphs' edges, one neighbour-order sort and one core-order
+ * sort. outs[i] equals what scan_build_index(&gs[i], ...) returns. All graphs
+ * must be device resident (on_device = 1) or all host resident. Errors as for
+ * scan_build_index; on error no index is returned. */
+scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_kind kind,
+                                   uint32_t flags, void *stream, scan_index **outs);
+
+/* Clustering query (mu, eps), Algorithms 3-5 of Section 4.2 with the border
+ * rule of Section 7.3.4. memberships: DEVICE pointer to int32[n]. Runs on the
+ * stream the index was built on; asynchronous.
+ * Errors: SCAN_EINVAL for a null pointer, mu < 2 or NaN eps. mu > dmax+1 is
+ * not an error: no vertex is a core and every entry is -1. */
+scan_status scan_query(const scan_index *ix, int32_t mu, double eps, int32_t *memberships);
+
+/* As scan_query, on `stream`, optionally also writing is_core (uint8[n],
+ * nullable). out_on_device = 0: memberships/is_core are host pointers and the
+ * call returns after they are written (synchronous). Concurrent calls on
+ * different streams are safe: each takes its own workspace. */
+scan_status scan_query_ex(const scan_index *ix, int32_t mu, double eps, int32_t *memberships,
+                          uint8_t *is_core, int32_t out_on_device, void *stream);
+
+/* `count` queries (mu[i], eps[i]) answered together in shared launches:
+ * memberships is int32[count * n], query i writing [i*n, (i+1)*n). mu and eps
+ * are HOST arrays. out_on_device as in scan_query_ex. Each result is identical
+ * to the single-query result. Errors: SCAN_EINVAL if any (mu, eps) is
+ * invalid (nothing is enqueued then). */
+scan_status scan_query_batch(const scan_index *ix, int32_t count, const int32_t *mu,
+                             const double *eps, int32_t *memberships, int32_t out_on_device,
+                             void *stream);
+
+scan_status scan_index_get_info(const scan_index *ix, scan_index_info *out);
+
+/* Copies one index array to host memory (synchronous). dst_bytes must be at
+ * least the array's size. SCAN_EINVAL for an array that was not kept. */
+scan_status scan_index_export(const scan_index *ix, scan_array what, void *host_dst,
+                              int64_t dst_bytes);
+
+/* Device pointer and byte size of one index array (valid until the index is
+ * freed; read only). */
+scan_status scan_index_device_ptr(const scan_index *ix, scan_array what, const void **ptr,
+                                  int64_t *bytes);
+
+/* Phase times of a build made with SCAN_PROFILE (waits for the build to
+ * finish). SCAN_EINVAL if the index was built without SCAN_PROFILE. */
+scan_status scan_index_build_profile(const scan_index *ix, scan_build_profile *out);
+
+/* Frees the index after the work enqueued on its stream completes.
+ * NULL is a no-op. */
+void scan_index_free(scan_index *ix);
+
+/* ---- Serving: continuous batching of (mu, eps) queries ----------------
+ * A server keeps one index resident and answers queries submitted from any
+ * host thread. Requests that arrive while others run are admitted as query
+ * slots and device memory free up, and join the next device batch; each
+ * result is identical to scan_query's. */
+typedef struct {
+  int32_t max_slots;        /* concurrent queries in flight (>= 1)            */
+  int32_t max_batch;        /* queries per device batch (>= 1)                */
+  int64_t memory_budget;    /* device bytes for query workspaces + outputs    */
+  int32_t use_graph;        /* 1: replay a captured HIP graph per batch       */
+} scan_server_opts;
+
+typedef struct scan_server scan_server;
+
+/* Errors: SCAN_EINVAL (bad opts), SCAN_ENOMEM (budget below one slot). */
+scan_status scan_server_create(const scan_index *ix, const scan_server_opts *opts,
+                               scan_server **out);
+/* Queues (mu, eps); the result is copied to host `dst` (int32[n]) when done.
+ * SCAN_EBUSY when no slot is free within the memory budget (nothing queued),
+ * SCAN_EINVAL for mu < 2 or NaN eps. *ticket identifies the request. */
+scan_status scan_server_submit(scan_server *s, int32_t mu, double eps, int32_t *dst,
+                               uint64_t *ticket);
+/* *done = 1 once the result for ticket is in dst. */
+scan_status scan_server_poll(scan_server *s, uint64_t ticket, int32_t *done);
+/* Blocks until the ticket completes. */
+scan_status scan_server_wait(scan_server *s, uint64_t ticket);
+/* Drains outstanding requests, then frees everything. NULL is a no-op. */
+void scan_server_destroy(scan_server *s);
+
+/* Diagnostic: evaluates the device similarity function the build uses on
+ * `count` triples (c[i], a_u[i], a_v[i]) given in HOST arrays and writes
+ * out[i] (host). Synchronous, on the default stream. For checking the device
+ * FP64 rounding (sqrt, division) against a host computation.
+ * Errors: SCAN_EINVAL (count < 0, null pointer with count > 0, unknown kind),
+ * SCAN_ENOMEM, SCAN_EDEVICE. */
+scan_status scan_similarity_values(scan_sim_kind kind, int64_t count, const int64_t *c,
+                                   const int64_t *a_u, const int64_t *a_v, double *out);
+
+/* Thread-local message describing the last failure on this thread. */
+const char *scan_last_error(void);
+
+/* Library version string. */
+const char *scan_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCAN_MI355X_H */

@@ -1,0 +1,420 @@
+"""Exact index-based SCAN on AMD MI355X — Python binding of libscan.so.
+
+Argument marshalling only: every step of the index build and of the queries
+runs in the HIP kernels of ``csrc/`` behind the C ABI of ``include/scan.h``.
+PyTorch provides device memory and streams. If libscan.so is missing or no
+GPU is visible, calls raise; there is no CPU fallback.
+
+Method: Tseng, Dhulipala and Shun, "Parallel Index-Based Structural Graph
+Clustering and Its Approximation" (SIGMOD 2021): similarities over closed
+neighbourhoods (Section 3.1), the neighbour/core-order index (Section 3.2,
+Algorithm 2) and (mu, eps) queries (Section 4.2, Algorithms 3-5; border rule
+of Section 7.3.4).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscan.so")
+
+SCAN_OK, SCAN_EINVAL, SCAN_EGRAPH, SCAN_ENOMEM, SCAN_EDEVICE, SCAN_EBUSY = 0, -1, -2, -3, -4, -5
+COSINE, JACCARD = 0, 1
+SCAN_VALIDATE, SCAN_KEEP_SIMS, SCAN_KEEP_COUNTS, SCAN_PROFILE = 1, 2, 4, 8
+(ARR_OFFSETS, ARR_NO_IDS, ARR_NO_SIM, ARR_CO_OFF, ARR_CO_IDS, ARR_CO_THR, ARR_SIMS,
+ ARR_COUNTS) = range(8)
+_ARR_DTYPE = {ARR_OFFSETS: np.int64, ARR_NO_IDS: np.int32, ARR_NO_SIM: np.float64,
+              ARR_CO_OFF: np.int64, ARR_CO_IDS: np.int32, ARR_CO_THR: np.float64,
+              ARR_SIMS: np.float64, ARR_COUNTS: np.int32}
+_STATUS = {SCAN_EINVAL: "SCAN_EINVAL", SCAN_EGRAPH: "SCAN_EGRAPH", SCAN_ENOMEM: "SCAN_ENOMEM",
+           SCAN_EDEVICE: "SCAN_EDEVICE", SCAN_EBUSY: "SCAN_EBUSY"}
+
+
+class ScanError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("offset_bits", ctypes.c_int32),
+                ("on_device", ctypes.c_int32), ("offsets", ctypes.c_void_p), ("adj", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("dmax", ctypes.c_int64),
+                ("kind", ctypes.c_int32), ("flags", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("prepare_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
+                ("intersect_ms", ctypes.c_double), ("no_sort_ms", ctypes.c_double),
+                ("core_order_ms", ctypes.c_double), ("intersect_launches", ctypes.c_int32),
+                ("owners", ctypes.c_int32)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64), ("use_graph", ctypes.c_int32)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+# Every symbol include/scan.h declares (checked by the CPU tests).
+EXPORTS = [
+    "scan_set_allocator", "scan_build_index", "scan_build_index_batch", "scan_query",
+    "scan_query_ex", "scan_query_batch", "scan_index_get_info", "scan_index_export",
+    "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
+    "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
+    "scan_version", "scan_similarity_values", "scan_index_build_profile",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libscan.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2012_11188_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, f64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_uint32, ctypes.c_uint64)
+    P = ctypes.POINTER
+    sig = {
+        "scan_set_allocator": ([_ALLOC_FN, _RELEASE_FN, vp], i32),
+        "scan_build_index": ([P(_Csr), i32, u32, vp, P(vp)], i32),
+        "scan_build_index_batch": ([P(_Csr), i32, i32, u32, vp, P(vp)], i32),
+        "scan_query": ([vp, i32, f64, vp], i32),
+        "scan_query_ex": ([vp, i32, f64, vp, vp, i32, vp], i32),
+        "scan_query_batch": ([vp, i32, vp, vp, vp, i32, vp], i32),
+        "scan_index_get_info": ([vp, P(_Info)], i32),
+        "scan_index_export": ([vp, i32, vp, i64], i32),
+        "scan_index_device_ptr": ([vp, i32, P(vp), P(i64)], i32),
+        "scan_index_free": ([vp], None),
+        "scan_server_create": ([vp, P(_ServerOpts), P(vp)], i32),
+        "scan_server_submit": ([vp, i32, f64, vp, P(u64)], i32),
+        "scan_server_poll": ([vp, u64, P(i32)], i32),
+        "scan_server_wait": ([vp, u64], i32),
+        "scan_server_destroy": ([vp], None),
+        "scan_last_error": ([], ctypes.c_char_p),
+        "scan_version": ([], ctypes.c_char_p),
+        "scan_similarity_values": ([i32, i64, vp, vp, vp, vp], i32),
+        "scan_index_build_profile": ([vp, P(_Profile)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != SCAN_OK:
+        raise ScanError(st, load_library().scan_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# Device memory and streams from PyTorch.
+
+_torch_hooks = None
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the SCAN library runs on the GPU only")
+    return torch
+
+
+def use_torch_allocator(enable: bool = True):
+    """Routes the library's device allocations through PyTorch's caching
+    allocator (stream ordered). Called on first use."""
+    global _torch_hooks
+    lib = load_library()
+    if not enable:
+        _check(lib.scan_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None))
+        _torch_hooks = None
+        return
+    torch = _torch()
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+        except Exception:
+            return None
+
+    def _release(ptr, nbytes, stream, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    hooks = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
+    _check(lib.scan_set_allocator(hooks[0], hooks[1], None))
+    _torch_hooks = hooks
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ready():
+    lib = load_library()
+    _torch()
+    if _torch_hooks is None:
+        use_torch_allocator(True)
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# Index
+
+
+@dataclass
+class IndexInfo:
+    n: int
+    nnz: int
+    dmax: int
+    kind: int
+    flags: int
+    device_bytes: int
+
+
+class Index:
+    """A device-resident SCAN index (NO + CO). Freed with the object."""
+
+    def __init__(self, handle: int, stream: int):
+        self._h = ctypes.c_void_p(handle)
+        self.stream = stream
+        self.info = scan_index_get_info(self)
+
+    @property
+    def n(self):
+        return self.info.n
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            load_library().scan_index_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _csr_struct(off, adj):
+    """Builds a scan_csr from torch tensors (device) or numpy arrays (host).
+    Returns (struct, keepalive)."""
+    try:
+        import torch
+        is_tensor = isinstance(off, torch.Tensor)
+    except ImportError:
+        is_tensor = False
+    if is_tensor:
+        if off.dtype not in (torch.int32, torch.int64) or adj.dtype != torch.int32:
+            raise TypeError("offsets must be int32/int64, adj int32")
+        if not (off.is_cuda and adj.is_cuda):
+            raise TypeError("torch tensors must be on the GPU (pass numpy arrays for host data)")
+        off, adj = off.contiguous(), adj.contiguous()
+        bits = 32 if off.dtype == torch.int32 else 64
+        c = _Csr(off.numel() - 1, adj.numel(), bits, 1, off.data_ptr(), adj.data_ptr() if adj.numel() else None)
+        return c, (off, adj)
+    off = np.ascontiguousarray(off)
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    if off.dtype not in (np.int32, np.int64):
+        off = off.astype(np.int64)
+    bits = 32 if off.dtype == np.int32 else 64
+    c = _Csr(len(off) - 1, len(adj), bits, 0, off.ctypes.data, adj.ctypes.data if len(adj) else None)
+    return c, (off, adj)
+
+
+def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None) -> Index:
+    """Builds the index (Algorithms 1 and 2) of the CSR graph (off, adj)."""
+    lib = _ready()
+    c, keep = _csr_struct(off, adj)
+    s = _stream_handle(stream)
+    out = ctypes.c_void_p()
+    _check(lib.scan_build_index(ctypes.byref(c), int(kind), int(flags), ctypes.c_void_p(s), ctypes.byref(out)))
+    del keep
+    return Index(out.value, s)
+
+
+def scan_build_index_batch(graphs, kind: int = COSINE, flags: int = 0, stream=None) -> list[Index]:
+    """Builds one index per (off, adj) graph in merged launches."""
+    lib = _ready()
+    structs, keep = [], []
+    for off, adj in graphs:
+        c, k = _csr_struct(off, adj)
+        structs.append(c)
+        keep.append(k)
+    arr = (_Csr * len(structs))(*structs)
+    outs = (ctypes.c_void_p * len(structs))()
+    s = _stream_handle(stream)
+    _check(lib.scan_build_index_batch(arr, len(structs), int(kind), int(flags), ctypes.c_void_p(s), outs))
+    return [Index(outs[i], s) for i in range(len(structs))]
+
+
+def scan_index_get_info(ix: Index) -> IndexInfo:
+    info = _Info()
+    _check(load_library().scan_index_get_info(ix._h, ctypes.byref(info)))
+    return IndexInfo(info.n, info.nnz, info.dmax, info.kind, info.flags, info.device_bytes)
+
+
+def _array_count(ix: Index, what: int) -> int:
+    i = ix.info
+    return {ARR_OFFSETS: i.n + 1, ARR_CO_OFF: i.dmax + 3}.get(what, i.nnz)
+
+
+def scan_index_export(ix: Index, what: int) -> np.ndarray:
+    """Copies one index array to host memory."""
+    out = np.empty(_array_count(ix, what), dtype=_ARR_DTYPE[what])
+    _check(load_library().scan_index_export(ix._h, int(what), out.ctypes.data if out.size else None, out.nbytes))
+    return out
+
+
+def scan_index_build_profile(ix: Index) -> dict:
+    """Per-phase device milliseconds of a build made with SCAN_PROFILE."""
+    p = _Profile()
+    _check(load_library().scan_index_build_profile(ix._h, ctypes.byref(p)))
+    return {name: getattr(p, name) for name, _ in _Profile._fields_}
+
+
+def scan_index_device_ptr(ix: Index, what: int):
+    p, b = ctypes.c_void_p(), ctypes.c_int64()
+    _check(load_library().scan_index_device_ptr(ix._h, int(what), ctypes.byref(p), ctypes.byref(b)))
+    return p.value, b.value
+
+
+def scan_query(ix: Index, mu: int, eps: float, memberships=None):
+    """(mu, eps) query on the index's stream; returns int32[n] on the GPU."""
+    torch = _torch()
+    lib = _ready()
+    if memberships is None:
+        memberships = torch.empty(ix.n, dtype=torch.int32, device="cuda")
+    _check(lib.scan_query(ix._h, int(mu), float(eps), ctypes.c_void_p(memberships.data_ptr() if ix.n else 0)))
+    return memberships
+
+
+def scan_query_ex(ix: Index, mu: int, eps: float, memberships=None, is_core=None, stream=None,
+                  out_on_device: bool = True):
+    """(mu, eps) query on `stream`; returns (memberships, is_core)."""
+    torch = _torch()
+    lib = _ready()
+    s = _stream_handle(stream)
+    if out_on_device:
+        if memberships is None:
+            memberships = torch.empty(ix.n, dtype=torch.int32, device="cuda")
+        if is_core is None:
+            is_core = torch.empty(ix.n, dtype=torch.uint8, device="cuda")
+        mp, cp = memberships.data_ptr(), is_core.data_ptr()
+    else:
+        if memberships is None:
+            memberships = np.empty(ix.n, np.int32)
+        if is_core is None:
+            is_core = np.empty(ix.n, np.uint8)
+        mp, cp = memberships.ctypes.data, is_core.ctypes.data
+    _check(lib.scan_query_ex(ix._h, int(mu), float(eps), ctypes.c_void_p(mp if ix.n else 0),
+                             ctypes.c_void_p(cp if ix.n else 0), int(out_on_device), ctypes.c_void_p(s)))
+    return memberships, is_core
+
+
+def scan_query_batch(ix: Index, mus, epss, out=None, stream=None, out_on_device: bool = True):
+    """Batched queries; returns int32[count, n] (GPU tensor or numpy)."""
+    torch = _torch()
+    lib = _ready()
+    mu = np.ascontiguousarray(mus, dtype=np.int32)
+    eps = np.ascontiguousarray(epss, dtype=np.float64)
+    if mu.shape != eps.shape:
+        raise ValueError("mu and eps differ in length")
+    count = len(mu)
+    s = _stream_handle(stream)
+    if out is None:
+        out = (torch.empty((count, ix.n), dtype=torch.int32, device="cuda") if out_on_device
+               else np.empty((count, ix.n), np.int32))
+    ptr = out.data_ptr() if out_on_device else out.ctypes.data
+    _check(lib.scan_query_batch(ix._h, count, mu.ctypes.data, eps.ctypes.data,
+                                ctypes.c_void_p(ptr if ix.n and count else 0), int(out_on_device), ctypes.c_void_p(s)))
+    return out
+
+
+def scan_similarity_values(kind: int, c, a_u, a_v) -> np.ndarray:
+    """Device similarity function on host triples (diagnostic)."""
+    lib = _ready()
+    c = np.ascontiguousarray(c, dtype=np.int64)
+    a = np.ascontiguousarray(a_u, dtype=np.int64)
+    b = np.ascontiguousarray(a_v, dtype=np.int64)
+    out = np.empty(len(c), np.float64)
+    _check(lib.scan_similarity_values(int(kind), len(c), c.ctypes.data, a.ctypes.data, b.ctypes.data,
+                                      out.ctypes.data))
+    return out
+
+
+def version() -> str:
+    return load_library().scan_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Server
+
+
+class Server:
+    """Continuous-batching query server over one resident index."""
+
+    def __init__(self, ix: Index, max_slots: int = 16, max_batch: int = 16,
+                 memory_budget: int = 1 << 30, use_graph: bool = True):
+        lib = _ready()
+        self.ix = ix
+        opts = _ServerOpts(max_slots, max_batch, memory_budget, int(use_graph))
+        h = ctypes.c_void_p()
+        _check(lib.scan_server_create(ix._h, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, mu: int, eps: float, dst: np.ndarray) -> int:
+        t = ctypes.c_uint64()
+        _check(load_library().scan_server_submit(self._h, int(mu), float(eps), dst.ctypes.data, ctypes.byref(t)))
+        return t.value
+
+    def try_submit(self, mu: int, eps: float, dst: np.ndarray):
+        t = ctypes.c_uint64()
+        st = load_library().scan_server_submit(self._h, int(mu), float(eps), dst.ctypes.data, ctypes.byref(t))
+        if st == SCAN_EBUSY:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(load_library().scan_server_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(load_library().scan_server_wait(self._h, ticket))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load_library().scan_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

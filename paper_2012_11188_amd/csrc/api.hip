@@ -1,0 +1,319 @@
+// C ABI of the library: argument checking, errors, device memory hooks, the
+// index object's accessors and the query entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "index.h"
+
+namespace scan {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+scan_status fail(scan_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+static std::mutex g_alloc_mu;
+static scan_alloc_fn g_alloc = nullptr;
+static scan_release_fn g_release = nullptr;
+static void *g_alloc_ctx = nullptr;
+
+void *dev_alloc(size_t bytes, hipStream_t stream) {
+  scan_alloc_fn a;
+  void *ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+    ctx = g_alloc_ctx;
+  }
+  if (a) return a(bytes, (void *)stream, ctx);
+  void *p = nullptr;
+  if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void *p, size_t bytes, hipStream_t stream) {
+  if (!p) return;
+  scan_release_fn r;
+  void *ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    r = g_release;
+    ctx = g_alloc_ctx;
+  }
+  if (r) {
+    r(p, bytes, (void *)stream, ctx);
+    return;
+  }
+  (void)hipFreeAsync(p, stream);
+}
+
+}  // namespace scan
+
+using namespace scan;
+
+static const int64_t kArrayElem[] = {8, 4, 8, 8, 4, 8, 8, 4};
+
+static scan_status array_of(const scan_index *ix, scan_array what, const void **p, int64_t *bytes) {
+  switch (what) {
+    case SCAN_ARR_OFFSETS: *p = ix->off; *bytes = (ix->n + 1) * 8; break;
+    case SCAN_ARR_NO_IDS: *p = ix->no_ids; *bytes = ix->nnz * 4; break;
+    case SCAN_ARR_NO_SIM: *p = ix->no_sim; *bytes = ix->nnz * 8; break;
+    case SCAN_ARR_CO_OFF: *p = ix->co_off; *bytes = (ix->dmax + 3) * 8; break;
+    case SCAN_ARR_CO_IDS: *p = ix->co_ids; *bytes = ix->nnz * 4; break;
+    case SCAN_ARR_CO_THR: *p = ix->co_thr; *bytes = ix->nnz * 8; break;
+    case SCAN_ARR_SIMS:
+      if (!ix->sims) return fail(SCAN_EINVAL, "similarities were not kept (build with SCAN_KEEP_SIMS)");
+      *p = ix->sims; *bytes = ix->nnz * 8; break;
+    case SCAN_ARR_COUNTS:
+      if (!ix->counts) return fail(SCAN_EINVAL, "counts were not kept (build with SCAN_KEEP_COUNTS)");
+      *p = ix->counts; *bytes = ix->nnz * 4; break;
+    default:
+      return fail(SCAN_EINVAL, "unknown array %d", (int)what);
+  }
+  (void)kArrayElem;
+  return SCAN_OK;
+}
+
+static scan_status check_query(const scan_index *ix, int32_t mu, double eps) {
+  if (!ix) return fail(SCAN_EINVAL, "null index");
+  if (mu < 2) return fail(SCAN_EINVAL, "mu must be >= 2 (got %d)", mu);
+  if (std::isnan(eps)) return fail(SCAN_EINVAL, "eps is NaN");
+  return SCAN_OK;
+}
+
+// Takes `count` query slots for use on stream s: a pooled slot is reusable if
+// it is not busy and either its last use was on s (stream order) or its
+// completion event has fired.
+static scan_status acquire_slots(scan_index *ix, int count, hipStream_t s,
+                                 std::vector<scan_index::PooledSlot *> &got) {
+  std::lock_guard<std::mutex> lk(ix->pool_mu);
+  for (auto *p : ix->pool) {
+    if ((int)got.size() == count) break;
+    if (p->busy) continue;
+    bool ok = p->last_stream == s || !p->done || hipEventQuery(p->done) == hipSuccess;
+    if (ok) {
+      p->busy = true;
+      got.push_back(p);
+    }
+  }
+  while ((int)got.size() < count) {
+    auto *p = new scan_index::PooledSlot();
+    scan_status st = alloc_query_slot(ix, &p->slot, s);
+    if (st != SCAN_OK) {
+      delete p;
+      for (auto *q : got) q->busy = false;
+      got.clear();
+      return st;
+    }
+    if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) p->done = nullptr;
+    p->busy = true;
+    ix->pool.push_back(p);
+    got.push_back(p);
+  }
+  return SCAN_OK;
+}
+
+static void release_slots(scan_index *ix, std::vector<scan_index::PooledSlot *> &got, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(ix->pool_mu);
+  for (auto *p : got) {
+    if (p->done) (void)hipEventRecord(p->done, s);
+    p->last_stream = s;
+    p->busy = false;
+  }
+  got.clear();
+}
+
+static scan_status query_impl(const scan_index *cix, int32_t count, const int32_t *mu,
+                              const double *eps, int32_t *memberships, uint8_t *is_core,
+                              int32_t out_on_device, hipStream_t s) {
+  scan_index *ix = const_cast<scan_index *>(cix);
+  const int64_t n = ix->n;
+  std::vector<scan_index::PooledSlot *> got;
+  SCAN_TRY(acquire_slots(ix, count, s, got));
+  std::vector<QuerySlot> slots(count);
+  for (int i = 0; i < count; ++i) slots[i] = got[i]->slot;
+  std::vector<int32_t *> mptr(count);
+  std::vector<uint8_t *> cptr(count, nullptr);
+  DevArena tmp(s);
+  int32_t *dm = memberships;
+  uint8_t *dc = is_core;
+  scan_status st = SCAN_OK;
+  if (!out_on_device) {
+    st = tmp.alloc(&dm, (int64_t)count * n);
+    if (st == SCAN_OK && is_core) st = tmp.alloc(&dc, (int64_t)count * n);
+  }
+  if (st == SCAN_OK) {
+    for (int i = 0; i < count; ++i) {
+      mptr[i] = dm + (int64_t)i * n;
+      if (dc) cptr[i] = dc + (int64_t)i * n;
+    }
+    st = run_queries(ix, count, mu, eps, mptr.data(), dc ? cptr.data() : nullptr, slots.data(), s);
+  }
+  if (st == SCAN_OK && !out_on_device && n > 0) {
+    hipError_t e = hipMemcpyAsync(memberships, dm, (size_t)count * n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && is_core)
+      e = hipMemcpyAsync(is_core, dc, (size_t)count * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(SCAN_EDEVICE, "result copy: %s", hipGetErrorString(e));
+  }
+  release_slots(ix, got, s);
+  return st;
+}
+
+extern "C" {
+
+scan_status scan_set_allocator(scan_alloc_fn alloc, scan_release_fn release, void *ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(SCAN_EINVAL, "alloc and release must both be set or both be NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc;
+  g_release = release;
+  g_alloc_ctx = ctx;
+  return SCAN_OK;
+}
+
+scan_status scan_build_index(const scan_csr *g, scan_sim_kind kind, uint32_t flags, void *stream,
+                             scan_index **out) {
+  if (!out) return fail(SCAN_EINVAL, "null output pointer");
+  *out = nullptr;
+  return build_index(g, (int32_t)kind, flags, (hipStream_t)stream, default_config(), out);
+}
+
+scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_kind kind,
+                                   uint32_t flags, void *stream, scan_index **outs) {
+  return build_index_batch(gs, count, (int32_t)kind, flags, (hipStream_t)stream, default_config(),
+                           outs);
+}
+
+scan_status scan_query(const scan_index *ix, int32_t mu, double eps, int32_t *memberships) {
+  SCAN_TRY(check_query(ix, mu, eps));
+  if (!memberships && ix->n > 0) return fail(SCAN_EINVAL, "null memberships");
+  return query_impl(ix, 1, &mu, &eps, memberships, nullptr, 1, ix->stream);
+}
+
+scan_status scan_query_ex(const scan_index *ix, int32_t mu, double eps, int32_t *memberships,
+                          uint8_t *is_core, int32_t out_on_device, void *stream) {
+  SCAN_TRY(check_query(ix, mu, eps));
+  if (!memberships && ix->n > 0) return fail(SCAN_EINVAL, "null memberships");
+  return query_impl(ix, 1, &mu, &eps, memberships, is_core, out_on_device, (hipStream_t)stream);
+}
+
+scan_status scan_query_batch(const scan_index *ix, int32_t count, const int32_t *mu,
+                             const double *eps, int32_t *memberships, int32_t out_on_device,
+                             void *stream) {
+  if (!ix) return fail(SCAN_EINVAL, "null index");
+  if (count < 0) return fail(SCAN_EINVAL, "negative count");
+  if (count == 0) return SCAN_OK;
+  if (!mu || !eps || (!memberships && ix->n > 0)) return fail(SCAN_EINVAL, "null argument");
+  for (int32_t i = 0; i < count; ++i) SCAN_TRY(check_query(ix, mu[i], eps[i]));
+  return query_impl(ix, count, mu, eps, memberships, nullptr, out_on_device, (hipStream_t)stream);
+}
+
+scan_status scan_index_get_info(const scan_index *ix, scan_index_info *out) {
+  if (!ix || !out) return fail(SCAN_EINVAL, "null argument");
+  out->n = ix->n;
+  out->nnz = ix->nnz;
+  out->dmax = ix->dmax;
+  out->kind = ix->kind;
+  out->flags = (int32_t)ix->flags;
+  out->device_bytes = ix->bytes;
+  return SCAN_OK;
+}
+
+scan_status scan_index_device_ptr(const scan_index *ix, scan_array what, const void **ptr,
+                                  int64_t *bytes) {
+  if (!ix || !ptr || !bytes) return fail(SCAN_EINVAL, "null argument");
+  return array_of(ix, what, ptr, bytes);
+}
+
+scan_status scan_index_export(const scan_index *ix, scan_array what, void *host_dst,
+                              int64_t dst_bytes) {
+  if (!ix) return fail(SCAN_EINVAL, "null index");
+  const void *p;
+  int64_t bytes;
+  SCAN_TRY(array_of(ix, what, &p, &bytes));
+  if (bytes > 0 && !host_dst) return fail(SCAN_EINVAL, "null destination");
+  if (dst_bytes < bytes) return fail(SCAN_EINVAL, "destination holds %lld bytes, need %lld", (long long)dst_bytes, (long long)bytes);
+  if (bytes == 0) return SCAN_OK;
+  SCAN_HIP_TRY(hipMemcpyAsync(host_dst, p, (size_t)bytes, hipMemcpyDeviceToHost, ix->stream));
+  SCAN_HIP_TRY(hipStreamSynchronize(ix->stream));
+  return SCAN_OK;
+}
+
+scan_status scan_index_build_profile(const scan_index *ix, scan_build_profile *out) {
+  if (!ix || !out) return fail(SCAN_EINVAL, "null argument");
+  if (!(ix->flags & SCAN_PROFILE) || !ix->ev[0]) return fail(SCAN_EINVAL, "index was built without SCAN_PROFILE");
+  SCAN_HIP_TRY(hipEventSynchronize(ix->ev[5]));
+  float t[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 1; k < 6; ++k) SCAN_HIP_TRY(hipEventElapsedTime(&t[k], ix->ev[k - 1], ix->ev[k]));
+  float total = 0;
+  SCAN_HIP_TRY(hipEventElapsedTime(&total, ix->ev[0], ix->ev[5]));
+  out->total_ms = total;
+  out->prepare_ms = t[1];
+  out->plan_ms = t[2];
+  out->intersect_ms = t[3];
+  out->no_sort_ms = t[4];
+  out->core_order_ms = t[5];
+  out->intersect_launches = ix->intersect_launches;
+  out->owners = ix->owners;
+  return SCAN_OK;
+}
+
+void scan_index_free(scan_index *ix) {
+  if (!ix) return;
+  for (auto &e : ix->ev)
+    if (e) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  {
+    std::lock_guard<std::mutex> lk(ix->pool_mu);
+    for (auto *p : ix->pool) {
+      if (p->done) {
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+      }
+      free_query_slot(&p->slot, ix->stream);
+      delete p;
+    }
+    ix->pool.clear();
+  }
+  index_release(ix);
+  delete ix;
+}
+
+const char *scan_last_error(void) { return g_err; }
+
+scan_status scan_similarity_values(scan_sim_kind kind, int64_t count, const int64_t *c,
+                                   const int64_t *a_u, const int64_t *a_v, double *out) {
+  if (count < 0) return fail(SCAN_EINVAL, "negative count");
+  if (kind != SCAN_SIM_COSINE && kind != SCAN_SIM_JACCARD) return fail(SCAN_EINVAL, "unknown kind");
+  if (count == 0) return SCAN_OK;
+  if (!c || !a_u || !a_v || !out) return fail(SCAN_EINVAL, "null argument");
+  return similarity_values((int32_t)kind, count, c, a_u, a_v, out);
+}
+
+const char *scan_version(void) { return "scan-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Index object and internal entry points shared by the library's host code.
+#pragma once
+
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace scan {
+
+// Tunable parameters of the intersection kernels (chosen per graph by the
+// autotuner or the defaults).
+struct IntersectConfig {
+  int32_t small_log_t = 8;   // smallest LDS table class (2^k int32 slots)
+  int32_t big_log_t = 14;    // largest table class; owners beyond half of it
+                             // are split into id-range parts
+  int32_t spc_small = 256;   // row slots per chunk, classes below big
+  int32_t spc_big = 1024;    // row slots per chunk, big class
+  int32_t waves_big = 8;     // waves per workgroup, big class
+};
+
+// Per-query device workspace (one slot of a batch).
+struct QuerySlot {
+  int32_t *parent = nullptr;  // int32[n] union-find parents (cores only)
+  uint8_t *flag = nullptr;    // uint8[n] candidate borders; all zero between queries
+  size_t bytes = 0;
+};
+
+struct QueryDesc;  // device-side query descriptor (query.hip)
+
+}  // namespace scan
+
+struct scan_index {
+  int64_t n = 0, nnz = 0, dmax = 0;
+  int32_t kind = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t *off = nullptr;      // int64[n+1]
+  int32_t *no_ids = nullptr;   // int32[nnz]
+  double *no_sim = nullptr;    // double[nnz]
+  int64_t *co_off = nullptr;   // int64[dmax+3]
+  int32_t *co_ids = nullptr;   // int32[nnz]
+  double *co_thr = nullptr;    // double[nnz]
+  double *sims = nullptr;      // double[nnz] (SCAN_KEEP_SIMS)
+  int32_t *counts = nullptr;   // int32[nnz]  (SCAN_KEEP_COUNTS)
+  struct Alloc {
+    void *p;
+    size_t bytes;
+  };
+  std::vector<Alloc> allocs;
+  // SCAN_PROFILE: events at phase boundaries (start, prepare, plan,
+  // intersect, neighbour order, core order).
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t intersect_launches = 0;
+  int32_t owners = 0;
+  int64_t bytes = 0;
+  // Query workspace pool: a slot may be reused once its last use completed
+  // (event) or when the new use is on the same stream.
+  struct PooledSlot {
+    scan::QuerySlot slot;
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool busy = false;
+  };
+  std::mutex pool_mu;
+  std::vector<PooledSlot *> pool;
+};
+
+namespace scan {
+
+scan_status index_alloc(scan_index *ix, void **p, size_t bytes);
+void index_release(scan_index *ix);
+
+scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStream_t stream,
+                        const IntersectConfig &cfg, scan_index **out);
+scan_status build_index_batch(const scan_csr *gs, int32_t count, int32_t kind, uint32_t flags,
+                              hipStream_t stream, const IntersectConfig &cfg, scan_index **outs);
+
+// Runs `count` queries. mu/eps host arrays; memberships[i] / is_core[i] are
+// device pointers (is_core may hold nulls). Slots are workspaces, one per
+// query.
+scan_status run_queries(const scan_index *ix, int32_t count, const int32_t *mu, const double *eps,
+                        int32_t *const *memberships, uint8_t *const *is_core,
+                        const QuerySlot *slots, hipStream_t s);
+
+scan_status alloc_query_slot(const scan_index *ix, QuerySlot *slot, hipStream_t s);
+void free_query_slot(QuerySlot *slot, hipStream_t s);
+
+IntersectConfig default_config();
+
+scan_status similarity_values(int32_t kind, int64_t count, const int64_t *c, const int64_t *a_u,
+                              const int64_t *a_v, double *out);
+
+}  // namespace scan

@@ -1,0 +1,229 @@
+// (mu, eps) clustering queries over the index (Section 4.2, Algorithms 3-5;
+// connectivity by union-find as in Section 6.2; border vertices by the
+// deterministic rule of Section 7.3.4).
+//
+// Per query, four grid-stride kernels over a batch (blockIdx.y = query):
+//   a7  k_q_cores   K = length of the eps-prefix of CO[mu] (binary search);
+//                   parent[u] = u for the K cores
+//   a8+a9 k_q_union for each core u, scan the eps-prefix of NO[u]; a core
+//                   neighbour w is united with u (larger root hooked under the
+//                   smaller, so every root is its component's smallest id); a
+//                   non-core neighbour is flagged as a candidate border
+//   a9  k_q_jump    parent[u] = find(u) for every core
+//   a10 k_q_output  memberships: cores -> root; flagged non-cores -> root of
+//                   the first core in their own NO row (NO is sorted by sim
+//                   desc, id asc, so that is the most similar eps-similar core,
+//                   ties to the lower id); others -1. Clears the flags.
+// A vertex w is a core iff deg(w) >= mu-1 and NO_SIM[off[w] + mu - 2] >= eps,
+// which is exactly membership in the eps-prefix of CO[mu].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "index.h"
+
+namespace scan {
+
+struct QueryDesc {
+  int32_t mu;
+  int32_t pad;
+  double eps;
+  int64_t base;  // co_off[mu] (0 if mu > dmax + 1)
+  int64_t K;     // number of cores
+  int32_t *parent;
+  uint8_t *flag;
+  int32_t *memb;
+  uint8_t *is_core;
+};
+
+struct IndexView {
+  int64_t n, dmax;
+  const int64_t *off;
+  const int32_t *no_ids;
+  const double *no_sim;
+  const int64_t *co_off;
+  const int32_t *co_ids;
+  const double *co_thr;
+};
+
+__device__ __forceinline__ bool core_test(const IndexView &ix, int32_t w, int32_t mu, double eps) {
+  int64_t o = ix.off[w];
+  int64_t d = ix.off[w + 1] - o;
+  return d >= (int64_t)mu - 1 && ix.no_sim[o + mu - 2] >= eps;
+}
+
+__device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x) {
+  int32_t cur = x;
+  for (;;) {
+    int32_t nxt = __atomic_load_n(&parent[cur], __ATOMIC_RELAXED);
+    if (nxt == cur) return cur;
+    int32_t nn = __atomic_load_n(&parent[nxt], __ATOMIC_RELAXED);
+    if (nn != nxt) __atomic_store_n(&parent[cur], nn, __ATOMIC_RELAXED);  // path halving
+    cur = nxt;
+  }
+}
+
+__device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) {
+  for (;;) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a < b) {
+      int32_t t = a;
+      a = b;
+      b = t;
+    }
+    // hook root a (larger) under b (smaller)
+    if (atomicCAS(&parent[a], a, b) == a) return;
+  }
+}
+
+__global__ void k_q_cores(IndexView ix, QueryDesc *qd) {
+  QueryDesc &q = qd[blockIdx.y];
+  // K by binary search (thread 0 of block 0 of this query's column)
+  __shared__ int64_t sK, sBase;
+  if (threadIdx.x == 0) {
+    int64_t K = 0, base = 0;
+    if ((int64_t)q.mu <= ix.dmax + 1) {
+      base = ix.co_off[q.mu];
+      int64_t lo = 0, hi = ix.co_off[q.mu + 1] - base;
+      while (lo < hi) {  // first position with thr < eps
+        int64_t mid = (lo + hi) >> 1;
+        if (ix.co_thr[base + mid] >= q.eps) lo = mid + 1;
+        else hi = mid;
+      }
+      K = lo;
+    }
+    sK = K;
+    sBase = base;
+    if (blockIdx.x == 0) {
+      q.K = K;
+      q.base = base;
+    }
+  }
+  __syncthreads();
+  int64_t K = sK, base = sBase;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < K;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = ix.co_ids[base + i];
+    q.parent[u] = u;
+  }
+}
+
+// One wavefront per core; lanes stride the eps-prefix of its NO row.
+__global__ void k_q_union(IndexView ix, const QueryDesc *qd) {
+  const QueryDesc q = qd[blockIdx.y];
+  int lane = threadIdx.x & (kWave - 1);
+  int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t i = w; i < q.K; i += nw) {
+    int32_t u = ix.co_ids[q.base + i];
+    int64_t b = ix.off[u], e = ix.off[u + 1];
+    for (int64_t k0 = b; k0 < e; k0 += kWave) {
+      int64_t k = k0 + lane;
+      bool in = k < e && ix.no_sim[k] >= q.eps;
+      if (in) {
+        int32_t x = ix.no_ids[k];
+        if (core_test(ix, x, q.mu, q.eps)) {
+          if (x < u) uf_union(q.parent, u, x);
+        } else {
+          q.flag[x] = 1;
+        }
+      }
+      if (!__all(in)) break;  // the prefix ended inside this chunk
+    }
+  }
+}
+
+__global__ void k_q_jump(IndexView ix, const QueryDesc *qd) {
+  const QueryDesc q = qd[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q.K;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = ix.co_ids[q.base + i];
+    q.parent[u] = uf_find(q.parent, u);
+  }
+}
+
+__global__ void k_q_output(IndexView ix, const QueryDesc *qd) {
+  const QueryDesc q = qd[blockIdx.y];
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < ix.n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    bool core = q.K > 0 && core_test(ix, (int32_t)v, q.mu, q.eps);
+    int32_t m = -1;
+    if (core) {
+      m = q.parent[v];
+    } else if (q.flag[v]) {
+      q.flag[v] = 0;
+      int64_t b = ix.off[v], e = ix.off[v + 1];
+      for (int64_t k = b; k < e && ix.no_sim[k] >= q.eps; ++k) {
+        int32_t x = ix.no_ids[k];
+        if (core_test(ix, x, q.mu, q.eps)) {
+          m = q.parent[x];
+          break;
+        }
+      }
+    }
+    q.memb[v] = m;
+    if (q.is_core) q.is_core[v] = core ? 1 : 0;
+  }
+}
+
+scan_status alloc_query_slot(const scan_index *ix, QuerySlot *slot, hipStream_t s) {
+  size_t n = (size_t)(ix->n > 0 ? ix->n : 1);
+  slot->bytes = n * 4 + n;
+  slot->parent = (int32_t *)dev_alloc(n * 4, s);
+  slot->flag = (uint8_t *)dev_alloc(n, s);
+  if (!slot->parent || !slot->flag) {
+    free_query_slot(slot, s);
+    return fail(SCAN_ENOMEM, "query workspace allocation failed");
+  }
+  hipError_t e = hipMemsetAsync(slot->flag, 0, n, s);
+  if (e != hipSuccess) return fail(SCAN_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+  return SCAN_OK;
+}
+
+void free_query_slot(QuerySlot *slot, hipStream_t s) {
+  size_t n = slot->bytes / 5;
+  if (slot->parent) dev_free(slot->parent, n * 4, s);
+  if (slot->flag) dev_free(slot->flag, n, s);
+  slot->parent = nullptr;
+  slot->flag = nullptr;
+}
+
+scan_status run_queries(const scan_index *ix, int32_t count, const int32_t *mu, const double *eps,
+                        int32_t *const *memberships, uint8_t *const *is_core,
+                        const QuerySlot *slots, hipStream_t s) {
+  if (count <= 0) return SCAN_OK;
+  std::vector<QueryDesc> h(count);
+  for (int32_t i = 0; i < count; ++i) {
+    h[i] = QueryDesc{mu[i], 0, eps[i], 0, 0, slots[i].parent, slots[i].flag, memberships[i],
+                     is_core ? is_core[i] : nullptr};
+  }
+  QueryDesc *d = (QueryDesc *)dev_alloc(sizeof(QueryDesc) * count, s);
+  if (!d) return fail(SCAN_ENOMEM, "query descriptor allocation failed");
+  hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(QueryDesc) * count, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    dev_free(d, sizeof(QueryDesc) * count, s);
+    return fail(SCAN_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+  }
+  // The descriptors are copied from pageable host memory: wait for the copy
+  // before the host vector goes out of scope.
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(SCAN_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  IndexView v{ix->n, ix->dmax, ix->off, ix->no_ids, ix->no_sim, ix->co_off, ix->co_ids, ix->co_thr};
+  int64_t n = ix->n > 0 ? ix->n : 1;
+  dim3 gc(grid_for(n, 256, 1024), count);
+  dim3 gu(grid_for(n * kWave, 256, 2048), count);
+  dim3 go(grid_for(n, 256, 2048), count);
+  k_q_cores<<<gc, 256, 0, s>>>(v, d);
+  k_q_union<<<gu, 256, 0, s>>>(v, d);
+  k_q_jump<<<gc, 256, 0, s>>>(v, d);
+  k_q_output<<<go, 256, 0, s>>>(v, d);
+  e = hipGetLastError();
+  dev_free(d, sizeof(QueryDesc) * count, s);
+  if (e != hipSuccess) return fail(SCAN_EDEVICE, "query launch: %s", hipGetErrorString(e));
+  return SCAN_OK;
+}
+
+}  // namespace scan
