@@ -82,217 +82,28 @@ __global__ void k_validate(const OffT *off, const int32_t *adj, int64_t n, int64
 }
 
 // ---------------------------------------------------------------------------
-// a2: ownership and chunk planning.
-
-__device__ __forceinline__ bool is_lower(int32_t u, int32_t du, int32_t h, int32_t dh) {
-  return du < dh || (du == dh && u < h);
-}
-
-struct Chunk {
-  int32_t h;  // owner
-  int32_t k;  // chunk index within row h
-};
-
-constexpr int kNumClasses = 8;  // table classes small_log_t .. big_log_t
-
-struct PlanStats {
-  int32_t chunks[kNumClasses];
-  int32_t owners;
-};
-
-// One wavefront per vertex h: counts its lower neighbours; if any, appends the
-// chunks covering row h to the list of h's table class.
-__global__ void k_plan(const int64_t *off, const int32_t *deg, const int32_t *adj, int64_t n,
-                       int small_log_t, int big_log_t, int spc_small, int spc_big, Chunk *lists,
-                       int64_t cap, PlanStats *st) {
-  int lane = threadIdx.x & (kWave - 1);
-  int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-  int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t h = w; h < n; h += nw) {
-    int32_t dh = deg[h];
-    if (dh == 0) continue;
-    int64_t b = off[h];
-    bool any_lower = false;
-    for (int64_t s = b + lane; s < b + dh && !any_lower; s += kWave) {
-      int32_t u = adj[s];
-      bool lw = is_lower(u, deg[u], (int32_t)h, dh);
-      any_lower = __any(lw);
-    }
-    if (!any_lower) continue;
-    int cls = 0;
-    while (small_log_t + cls < big_log_t && (int64_t)dh > ((int64_t)1 << (small_log_t + cls - 1)))
-      ++cls;
-    int spc = (small_log_t + cls == big_log_t) ? spc_big : spc_small;
-    int32_t nch = (dh + spc - 1) / spc;
-    int32_t base = 0;
-    if (lane == 0) {
-      base = atomicAdd(&st->chunks[cls], nch);
-      atomicAdd(&st->owners, 1);
-    }
-    base = __shfl(base, 0, kWave);
-    for (int32_t k = lane; k < nch; k += kWave) lists[cls * cap + base + k] = Chunk{(int32_t)h, k};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// a3 + a4: intersection and similarity.
-
-__device__ __forceinline__ uint32_t hash_slot(int32_t x, int log_t) {
-  return ((uint32_t)x * 0x9E3779B1u) >> (32 - log_t);
-}
-
-// One workgroup per chunk (owner h, row slots [s0, s1)). The row of h is
-// inserted into the LDS table part by part (parts of at most 2^(LOG_T-1)
-// ids, covering consecutive id ranges); for every lower neighbour u in the
-// chunk one wavefront streams the part of N(u) inside the current id range
-// and counts table hits.
-template <int LOG_T>
-__global__ __launch_bounds__(512) void k_intersect(const Chunk *chunks, int32_t nchunks, int spc,
-                                                   const int64_t *off, const int32_t *deg,
-                                                   const int32_t *adj, int kind, double *sims,
-                                                   int32_t *counts) {
-  constexpr int T = 1 << LOG_T;
-  constexpr int CAP = T / 2;
-  extern __shared__ unsigned char smem[];
-  int32_t *tab = (int32_t *)smem;
-  int32_t *cnt = tab + T;
-  int64_t *mir = (int64_t *)(cnt + ((spc + 1) & ~1));
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int nwaves = blockDim.x / kWave;
-
-  for (int32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
-    const Chunk ch = chunks[ci];
-    const int32_t h = ch.h;
-    const int32_t dh = deg[h];
-    const int64_t oh = off[h];
-    const int64_t s0 = oh + (int64_t)ch.k * spc;
-    const int m = (int)min((int64_t)spc, oh + dh - s0);
-    const int parts = (dh + CAP - 1) / CAP;
-    __syncthreads();
-    for (int e = threadIdx.x; e < m; e += blockDim.x) {
-      cnt[e] = 0;
-      mir[e] = -1;
-    }
-    for (int p = 0; p < parts; ++p) {
-      const int p0 = p * CAP, p1 = min(dh, p0 + CAP);
-      const int32_t lo = p == 0 ? INT32_MIN : adj[oh + p0];
-      const int32_t hi = p == parts - 1 ? INT32_MAX : adj[oh + p1];
-      __syncthreads();
-      for (int i = threadIdx.x; i < T; i += blockDim.x) tab[i] = -1;
-      __syncthreads();
-      for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
-        int32_t x = adj[oh + i];
-        uint32_t pos = hash_slot(x, LOG_T);
-        while (atomicCAS(&tab[pos], -1, x) != -1) pos = (pos + 1) & (T - 1);
-      }
-      __syncthreads();
-      for (int e = wave; e < m; e += nwaves) {
-        const int32_t u = adj[s0 + e];
-        const int32_t du = deg[u];
-        if (!is_lower(u, du, h, dh)) continue;
-        const int64_t ou = off[u];
-        int64_t b0 = 0, b1 = du;
-        if (parts > 1) {
-          // positions in N(u) with lo <= x < hi (all lanes search alike)
-          int64_t a = 0, z = du;
-          while (a < z) {
-            int64_t mid = (a + z) >> 1;
-            if (adj[ou + mid] < lo) a = mid + 1;
-            else z = mid;
-          }
-          b0 = a;
-          z = du;
-          while (a < z) {
-            int64_t mid = (a + z) >> 1;
-            if (adj[ou + mid] < hi) a = mid + 1;
-            else z = mid;
-          }
-          b1 = a;
-        }
-        int32_t t = 0;
-        int64_t mpos = -1;
-        for (int64_t base = b0; base < b1; base += kWave) {
-          int64_t i = base + lane;
-          bool valid = i < b1;
-          int32_t x = valid ? adj[ou + i] : -1;
-          bool hit = false;
-          if (valid) {
-            uint32_t pos = hash_slot(x, LOG_T);
-            for (;;) {
-              int32_t y = tab[pos];
-              if (y == x) { hit = true; break; }
-              if (y == -1) break;
-              pos = (pos + 1) & (T - 1);
-            }
-          }
-          t += __popcll(__ballot(hit));
-          unsigned long long own = __ballot(valid && x == h);
-          if (own) mpos = ou + base + (__ffsll(own) - 1);
-        }
-        if (lane == 0) {
-          cnt[e] += t;
-          if (mpos >= 0) mir[e] = mpos;
-        }
-      }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m; e += blockDim.x) {
-      const int64_t s = s0 + e;
-      const int32_t u = adj[s];
-      const int32_t du = deg[u];
-      if (!is_lower(u, du, h, dh)) continue;
-      const int64_t c = (int64_t)cnt[e] + 2;
-      const double x = similarity(kind, c, (int64_t)du + 1, (int64_t)dh + 1);
-      sims[s] = x;
-      if (mir[e] >= 0) sims[mir[e]] = x;
-      if (counts) {
-        counts[s] = (int32_t)c;
-        if (mir[e] >= 0) counts[mir[e]] = (int32_t)c;
-      }
-    }
-  }
-}
-
-template <int LOG_T>
-static void launch_intersect(const Chunk *chunks, int32_t nchunks, int spc, int waves,
-                             const int64_t *off, const int32_t *deg, const int32_t *adj, int kind,
-                             double *sims, int32_t *counts, hipStream_t s) {
-  size_t lds = (size_t)(1 << LOG_T) * 4 + (size_t)((spc + 1) & ~1) * 4 + (size_t)spc * 8;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void *)k_intersect<LOG_T>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  k_intersect<LOG_T><<<grid_for(nchunks, 1, 1 << 20), waves * kWave, lds, s>>>(
-      chunks, nchunks, spc, off, deg, adj, kind, sims, counts);
-}
-
-static scan_status intersect_class(int log_t, const Chunk *chunks, int32_t nchunks, int spc,
-                                   int waves, const int64_t *off, const int32_t *deg,
-                                   const int32_t *adj, int kind, double *sims, int32_t *counts,
-                                   hipStream_t s) {
-  switch (log_t) {
-#define SCAN_CASE(L) \
-  case L: launch_intersect<L>(chunks, nchunks, spc, waves, off, deg, adj, kind, sims, counts, s); break;
-    SCAN_CASE(7) SCAN_CASE(8) SCAN_CASE(9) SCAN_CASE(10) SCAN_CASE(11) SCAN_CASE(12)
-    SCAN_CASE(13) SCAN_CASE(14) SCAN_CASE(15)
-#undef SCAN_CASE
-    default:
-      return fail(SCAN_EINVAL, "unsupported table class 2^%d", log_t);
-  }
-  SCAN_HIP_TRY(hipGetLastError());
-  return SCAN_OK;
-}
-
-// ---------------------------------------------------------------------------
 // a6: core order placement. With E = exclusive prefix of the degree
 // histogram, |CO[mu]| = n - E[mu-1]; vertex v gets a rank r(v) among the
 // vertices of degree >= deg(v) (vertices of higher degree first), so its
 // entry for mu = j + 2 lands at co_off[mu] + r(v), inside segment mu.
 
-__global__ void k_degree_hist(const int32_t *deg, int64_t n, int32_t *hist) {
+constexpr int kHistBins = 2048;  // degrees below this are binned in LDS first
+
+__global__ __launch_bounds__(256) void k_degree_hist(const int32_t *deg, int64_t n, int64_t dmax,
+                                                     int32_t *hist) {
+  __shared__ int32_t lh[kHistBins];
+  const int bins = (int)min((int64_t)kHistBins, dmax + 1);
+  for (int i = threadIdx.x; i < bins; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[deg[v]], 1);
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t d = deg[v];
+    if (d < kHistBins) atomicAdd(&lh[d], 1);
+    else atomicAdd(&hist[d], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < bins; i += blockDim.x)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
 }
 
 __global__ void k_co_sizes(const int64_t *E, int64_t n, int64_t dmax, int64_t *sizes) {
@@ -307,23 +118,71 @@ __global__ void k_co_finish_off(const int64_t *scan, int64_t dmax, int64_t *co_o
     co_off[i] = i < 2 ? 0 : scan[i - 2];
 }
 
-__global__ void k_co_place(const int64_t *off, const int32_t *deg, int64_t n, const int64_t *E,
-                           int32_t *cursor, const int64_t *co_off, const double *no_sim,
-                           double *co_key, int32_t *co_id) {
-  int lane = threadIdx.x & (kWave - 1);
-  int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-  int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t v = w; v < n; v += nw) {
-    int32_t d = deg[v];
-    if (d == 0) continue;
-    int64_t r = 0;
-    if (lane == 0) r = (n - E[d + 1]) + atomicAdd(&cursor[d], 1);
-    r = __shfl(r, 0, kWave);
-    int64_t o = off[v];
-    for (int32_t j = lane; j < d; j += kWave) {
-      int64_t pos = co_off[j + 2] + r;
-      co_key[pos] = no_sim[o + j];
-      co_id[pos] = (int32_t)v;
+// One workgroup per tile of kPlaceTile consecutive vertices: ranks within a
+// degree come from LDS counters plus one global reservation per (tile,
+// degree); rows of degree <= 32 are written by their own thread, longer rows
+// by a whole wavefront.
+constexpr int kPlaceTile = 1024;
+
+__global__ __launch_bounds__(256) void k_co_place(const int64_t *off, const int32_t *deg, int64_t n,
+                                                  int64_t dmax, const int64_t *E, int32_t *cursor,
+                                                  const int64_t *co_off, const double *no_sim,
+                                                  double *co_key, int32_t *co_id) {
+  __shared__ int32_t lcnt[kHistBins];
+  __shared__ int32_t rank[kPlaceTile];
+  __shared__ int32_t longv[kPlaceTile];
+  __shared__ int32_t nlong;
+  constexpr int kPer = kPlaceTile / 256;
+  const int bins = (int)min((int64_t)kHistBins, dmax + 1);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int64_t t0 = (int64_t)blockIdx.x * kPlaceTile; t0 < n; t0 += (int64_t)gridDim.x * kPlaceTile) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) lcnt[i] = 0;
+    if (threadIdx.x == 0) nlong = 0;
+    __syncthreads();
+    int32_t lr[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t v = t0 + k * 256 + threadIdx.x;
+      const int32_t d = v < n ? deg[v] : 0;
+      lr[k] = -1;
+      if (d > 0) lr[k] = d < kHistBins ? atomicAdd(&lcnt[d], 1) : atomicAdd(&cursor[d], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += blockDim.x)
+      if (lcnt[i]) lcnt[i] = atomicAdd(&cursor[i], lcnt[i]);  // tile's base within degree i
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int loc = k * 256 + threadIdx.x;
+      const int64_t v = t0 + loc;
+      if (v >= n || lr[k] < 0) continue;
+      const int32_t d = deg[v];
+      const int64_t r = (n - E[d + 1]) + (d < kHistBins ? lcnt[d] + lr[k] : lr[k]);
+      if (d <= 32) {
+        const int64_t o = off[v];
+        for (int32_t j = 0; j < d; ++j) {
+          const int64_t pos = co_off[j + 2] + r;
+          co_key[pos] = no_sim[o + j];
+          co_id[pos] = (int32_t)v;
+        }
+      } else {
+        rank[loc] = (int32_t)r;
+        longv[atomicAdd(&nlong, 1)] = loc;
+      }
+    }
+    __syncthreads();
+    for (int i = wave; i < nlong; i += blockDim.x / kWave) {
+      const int loc = longv[i];
+      const int64_t v = t0 + loc;
+      const int32_t d = deg[v];
+      const int64_t r = rank[loc];
+      const int64_t o = off[v];
+      for (int32_t j = lane; j < d; j += kWave) {
+        const int64_t pos = co_off[j + 2] + r;
+        co_key[pos] = no_sim[o + j];
+        co_id[pos] = (int32_t)v;
+      }
     }
   }
 }
@@ -401,9 +260,8 @@ scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStre
   SCAN_TRY(check_csr(g));
   if (kind != SCAN_SIM_COSINE && kind != SCAN_SIM_JACCARD) return fail(SCAN_EINVAL, "unknown similarity kind %d", kind);
   if (flags & ~(uint32_t)(SCAN_VALIDATE | SCAN_KEEP_SIMS | SCAN_KEEP_COUNTS | SCAN_PROFILE)) return fail(SCAN_EINVAL, "unknown build flags 0x%x", flags);
-  if (cfg.small_log_t < 7 || cfg.big_log_t > 15 || cfg.small_log_t > cfg.big_log_t ||
-      cfg.big_log_t - cfg.small_log_t >= kNumClasses || cfg.spc_small < 1 || cfg.spc_big < 1 ||
-      cfg.waves_big < 1 || cfg.waves_big > 8)
+  if (cfg.small_max < 1 || cfg.small_max > 4096 || cfg.spc < 1 || cfg.spc > 1024 || cfg.wbits < 10 ||
+      cfg.wbits > 24)
     return fail(SCAN_EINVAL, "bad intersection config");
   const int64_t n = g->n, nnz = g->nnz;
   const int osz = g->offset_bits / 8;
@@ -426,31 +284,24 @@ scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStre
   auto mark = [&](int k) {
     if (prof) (void)hipEventRecord(ix->ev[k], s);
   };
-  // The largest table class must fit the device's LDS per workgroup.
-  IntersectConfig cf = cfg;
-  {
-    int lds_max = 65536;
-    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device);
-    auto lds_of = [&](int log_t) { return ((size_t)1 << log_t) * 4 + (size_t)((cf.spc_big + 1) & ~1) * 4 + (size_t)cf.spc_big * 8; };
-    while (cf.big_log_t > cf.small_log_t && lds_of(cf.big_log_t) > (size_t)lds_max) --cf.big_log_t;
-  }
   auto bail = [&](scan_status st) {
+    for (auto &e : ix->ev)
+      if (e) (void)hipEventDestroy(e);
     index_release(ix);
     delete ix;
     return st;
   };
-#define BTRY(expr)                      \
-  do {                                  \
-    scan_status st_ = (expr);           \
+#define BTRY(expr)                        \
+  do {                                    \
+    scan_status st_ = (expr);             \
     if (st_ != SCAN_OK) return bail(st_); \
   } while (0)
-#define BHIP(expr)                                                                      \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return bail(fail(SCAN_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)));   \
+#define BHIP(expr)                                                                    \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return bail(fail(SCAN_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_))); \
   } while (0)
-
   DevArena tmp(s);
   mark(0);
   Staged in{g->offsets, g->adj};
@@ -521,32 +372,18 @@ scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStre
     return SCAN_OK;
   }
 
-  // a2: plan chunks per table class.
-  const int ncls = cf.big_log_t - cf.small_log_t + 1;
-  const int64_t cap = n + nnz / std::min(cf.spc_small, cf.spc_big) + 1;
-  Chunk *lists;
-  PlanStats *d_plan;
-  BTRY(tmp.alloc(&lists, cap * ncls));
-  BTRY(tmp.alloc(&d_plan, 1));
-  BHIP(hipMemsetAsync(d_plan, 0, sizeof(PlanStats), s));
-  k_plan<<<grid_for(n * kWave, 256), 256, 0, s>>>(ix->off, deg, in.adj, n, cf.small_log_t, cf.big_log_t,
-                                                  cf.spc_small, cf.spc_big, lists, cap, d_plan);
-  PlanStats plan;
-  BHIP(hipMemcpyAsync(&plan, d_plan, sizeof(plan), hipMemcpyDeviceToHost, s));
-  BHIP(hipStreamSynchronize(s));
-  ix->owners = plan.owners;
-  mark(2);
-
-  // a3 + a4: one launch per class.
-  for (int c = 0; c < ncls; ++c) {
-    if (!plan.chunks[c]) continue;
-    int log_t = cf.small_log_t + c;
-    bool big = log_t == cf.big_log_t;
-    BTRY(intersect_class(log_t, lists + c * cap, plan.chunks[c], big ? cf.spc_big : cf.spc_small,
-                         big ? cf.waves_big : 4, ix->off, deg, in.adj, kind, sims, ix->counts, s));
-    ++ix->intersect_launches;
+  // a2-a4: ownership plan, intersection and similarity.
+  {
+    IntersectStats ist;
+    if (prof) {
+      ist.ev_start = ix->ev[2];
+      ist.ev_end = ix->ev[3];
+    }
+    BTRY(intersect_all(cfg, n, nnz, ix->off, deg, in.adj, kind, sims, ix->counts, ix->device, s,
+                       &ist));
+    ix->owners = ist.owners_small;
+    ix->intersect_launches = (ist.owners_small > 0) + (ist.chunks_big > 0);
   }
-  mark(3);
 
   // a5: neighbour order = rows sorted by (sim desc, id asc).
   BTRY(segmented_sort(ix->off, n, nnz, sims, in.adj, ix->no_sim, ix->no_ids, s));
@@ -567,13 +404,13 @@ scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStre
   BTRY(tmp.alloc(&co_id, nnz));
   BHIP(hipMemsetAsync(hist, 0, (size_t)(dmax + 1) * 4, s));
   BHIP(hipMemsetAsync(cursor, 0, (size_t)(dmax + 1) * 4, s));
-  k_degree_hist<<<grid_for(n, 256), 256, 0, s>>>(deg, n, hist);
+  k_degree_hist<<<grid_for(n, 256, 1024), 256, 0, s>>>(deg, n, dmax, hist);
   BTRY(exclusive_scan(hist, E, dmax + 1, scan_ws, s));
   k_co_sizes<<<grid_for(dmax, 256), 256, 0, s>>>(E, n, dmax, sizes);
   BTRY(exclusive_scan64(sizes, co_scan, dmax, scan_ws, s));
   k_co_finish_off<<<grid_for(dmax + 3, 256), 256, 0, s>>>(co_scan, dmax, ix->co_off);
-  k_co_place<<<grid_for(n * kWave, 256), 256, 0, s>>>(ix->off, deg, n, E, cursor, ix->co_off, ix->no_sim,
-                                                     co_key, co_id);
+  k_co_place<<<grid_for(n, kPlaceTile, 4096), 256, 0, s>>>(ix->off, deg, n, dmax, E, cursor, ix->co_off,
+                                                           ix->no_sim, co_key, co_id);
   BTRY(segmented_sort(ix->co_off + 2, dmax, nnz, co_key, co_id, ix->co_thr, ix->co_ids, s));
   mark(5);
   BHIP(hipGetLastError());

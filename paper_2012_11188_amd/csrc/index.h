@@ -11,13 +11,24 @@ namespace scan {
 // Tunable parameters of the intersection kernels (chosen per graph by the
 // autotuner or the defaults).
 struct IntersectConfig {
-  int32_t small_log_t = 8;   // smallest LDS table class (2^k int32 slots)
-  int32_t big_log_t = 14;    // largest table class; owners beyond half of it
-                             // are split into id-range parts
-  int32_t spc_small = 256;   // row slots per chunk, classes below big
-  int32_t spc_big = 1024;    // row slots per chunk, big class
-  int32_t waves_big = 8;     // waves per workgroup, big class
+  int32_t small_max = 256;  // owners of degree <= small_max: one wavefront each
+  int32_t spc = 512;        // row slots per chunk of a larger owner
+  int32_t wbits = 20;       // LDS bitmap window of 2^wbits ids (clamped to LDS)
 };
+
+struct IntersectStats {
+  int32_t owners_small = 0;
+  int32_t chunks_big = 0;
+  int32_t wbits = 0;
+  hipEvent_t ev_start = nullptr;  // recorded after planning, before the first launch
+  hipEvent_t ev_end = nullptr;    // recorded after the last launch
+};
+
+// a2-a4: ownership plan, then intersection + similarity for every edge,
+// written into both CSR slots of sims (and counts if non-null).
+scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
+                          const int32_t *deg, const int32_t *adj, int kind, double *sims,
+                          int32_t *counts, int device, hipStream_t s, IntersectStats *stats);
 
 // Per-query device workspace (one slot of a batch).
 struct QuerySlot {

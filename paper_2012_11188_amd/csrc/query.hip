@@ -53,15 +53,19 @@ __device__ __forceinline__ bool core_test(const IndexView &ix, int32_t w, int32_
   return d >= (int64_t)mu - 1 && ix.no_sim[o + mu - 2] >= eps;
 }
 
+// parent[] is reset to the identity for every vertex before each query, so it
+// is always a forest (hooks go from a root to a smaller root, halving moves a
+// pointer to an ancestor); the step cap only guards against a corrupt index.
 __device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x) {
   int32_t cur = x;
-  for (;;) {
+  for (int guard = 0; guard < (1 << 26); ++guard) {
     int32_t nxt = __atomic_load_n(&parent[cur], __ATOMIC_RELAXED);
     if (nxt == cur) return cur;
     int32_t nn = __atomic_load_n(&parent[nxt], __ATOMIC_RELAXED);
     if (nn != nxt) __atomic_store_n(&parent[cur], nn, __ATOMIC_RELAXED);  // path halving
     cur = nxt;
   }
+  return cur;
 }
 
 __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) {
@@ -81,9 +85,9 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
 
 __global__ void k_q_cores(IndexView ix, QueryDesc *qd) {
   QueryDesc &q = qd[blockIdx.y];
-  // K by binary search (thread 0 of block 0 of this query's column)
-  __shared__ int64_t sK, sBase;
-  if (threadIdx.x == 0) {
+  // K by binary search (thread 0 of block 0 of this query's column); every
+  // parent entry starts as the identity.
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     int64_t K = 0, base = 0;
     if ((int64_t)q.mu <= ix.dmax + 1) {
       base = ix.co_off[q.mu];
@@ -95,20 +99,12 @@ __global__ void k_q_cores(IndexView ix, QueryDesc *qd) {
       }
       K = lo;
     }
-    sK = K;
-    sBase = base;
-    if (blockIdx.x == 0) {
-      q.K = K;
-      q.base = base;
-    }
+    q.K = K;
+    q.base = base;
   }
-  __syncthreads();
-  int64_t K = sK, base = sBase;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < K;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t u = ix.co_ids[base + i];
-    q.parent[u] = u;
-  }
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < ix.n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    q.parent[v] = (int32_t)v;
 }
 
 // One wavefront per core; lanes stride the eps-prefix of its NO row.

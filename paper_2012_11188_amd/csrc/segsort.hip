@@ -129,19 +129,38 @@ __device__ __forceinline__ int passes_for(int64_t len) {
   return p;
 }
 
-__global__ void k_classify(const int64_t *seg_off, int64_t nseg, int32_t *lists, int64_t cap,
-                           SortStats *st, int32_t *big_tiles_of) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t len = seg_off[i + 1] - seg_off[i];
-    if (len == 0) continue;
-    int c = len <= 1 ? kClsCopy : len <= kWave ? kClsWave : len <= kSmallTile ? kClsSmall
+// Wave-aggregated appends: one global atomic per (wavefront, class).
+__global__ __launch_bounds__(256) void k_classify(const int64_t *seg_off, int64_t nseg,
+                                                  int32_t *lists, int64_t cap, SortStats *st,
+                                                  int32_t *big_tiles_of) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nseg;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    int c = -1;
+    int64_t len = 0;
+    if (i < nseg) {
+      len = seg_off[i + 1] - seg_off[i];
+      if (len > 0)
+        c = len <= 1 ? kClsCopy : len <= kWave ? kClsWave : len <= kSmallTile ? kClsSmall
             : len <= kBigTile ? kClsMid : kClsBig;
-    int pos = atomicAdd(&st->count[c], 1);
-    lists[c * cap + pos] = (int32_t)i;
+    }
+    int32_t tiles = c == kClsBig ? (int32_t)((len + kBigTile - 1) / kBigTile) : 0;
+    for (int k = 0; k < kNumCls; ++k) {
+      const uint64_t m = __ballot(c == k);
+      if (!m) continue;
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int32_t b = 0;
+      if (lane == leader) b = atomicAdd(&st->count[k], __popcll(m));
+      b = __shfl(b, leader, kWave);
+      if (c == k) {
+        const int pos = b + __popcll(m & below);
+        lists[k * cap + pos] = (int32_t)i;
+        if (k == kClsBig) big_tiles_of[pos] = tiles;
+      }
+    }
     if (c == kClsBig) {
-      int32_t tiles = (int32_t)((len + kBigTile - 1) / kBigTile);
-      big_tiles_of[pos] = tiles;
       atomicAdd(&st->big_tiles, tiles);
       atomicMax(&st->max_passes, passes_for(len));
     }
