@@ -118,27 +118,20 @@ __global__ void k_co_finish_off(const int64_t *scan, int64_t dmax, int64_t *co_o
     co_off[i] = i < 2 ? 0 : scan[i - 2];
 }
 
-// One workgroup per tile of kPlaceTile consecutive vertices: ranks within a
-// degree come from LDS counters plus one global reservation per (tile,
-// degree); rows of degree <= 32 are written by their own thread, longer rows
-// by a whole wavefront.
-constexpr int kPlaceTile = 1024;
+// Rank of every non-isolated vertex in degree-descending order (ties in any
+// order: each CO segment is sorted afterwards). One workgroup per tile of
+// kRankTile consecutive vertices: LDS counters per degree plus one global
+// reservation per (tile, degree). sv[r] = vertex of rank r.
+constexpr int kRankTile = 1024;
 
-__global__ __launch_bounds__(256) void k_co_place(const int64_t *off, const int32_t *deg, int64_t n,
-                                                  int64_t dmax, const int64_t *E, int32_t *cursor,
-                                                  const int64_t *co_off, const double *no_sim,
-                                                  double *co_key, int32_t *co_id) {
+__global__ __launch_bounds__(256) void k_co_rank(const int32_t *deg, int64_t n, int64_t dmax,
+                                                 const int64_t *E, int32_t *cursor, int32_t *sv) {
   __shared__ int32_t lcnt[kHistBins];
-  __shared__ int32_t rank[kPlaceTile];
-  __shared__ int32_t longv[kPlaceTile];
-  __shared__ int32_t nlong;
-  constexpr int kPer = kPlaceTile / 256;
+  constexpr int kPer = kRankTile / 256;
   const int bins = (int)min((int64_t)kHistBins, dmax + 1);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  for (int64_t t0 = (int64_t)blockIdx.x * kPlaceTile; t0 < n; t0 += (int64_t)gridDim.x * kPlaceTile) {
+  for (int64_t t0 = (int64_t)blockIdx.x * kRankTile; t0 < n; t0 += (int64_t)gridDim.x * kRankTile) {
     __syncthreads();
     for (int i = threadIdx.x; i < bins; i += blockDim.x) lcnt[i] = 0;
-    if (threadIdx.x == 0) nlong = 0;
     __syncthreads();
     int32_t lr[kPer];
 #pragma unroll
@@ -150,38 +143,84 @@ __global__ __launch_bounds__(256) void k_co_place(const int64_t *off, const int3
     }
     __syncthreads();
     for (int i = threadIdx.x; i < bins; i += blockDim.x)
-      if (lcnt[i]) lcnt[i] = atomicAdd(&cursor[i], lcnt[i]);  // tile's base within degree i
+      if (lcnt[i]) lcnt[i] = atomicAdd(&cursor[i], lcnt[i]);  // the tile's base within degree i
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int loc = k * 256 + threadIdx.x;
-      const int64_t v = t0 + loc;
+      const int64_t v = t0 + k * 256 + threadIdx.x;
       if (v >= n || lr[k] < 0) continue;
       const int32_t d = deg[v];
       const int64_t r = (n - E[d + 1]) + (d < kHistBins ? lcnt[d] + lr[k] : lr[k]);
-      if (d <= 32) {
-        const int64_t o = off[v];
-        for (int32_t j = 0; j < d; ++j) {
-          const int64_t pos = co_off[j + 2] + r;
-          co_key[pos] = no_sim[o + j];
-          co_id[pos] = (int32_t)v;
-        }
-      } else {
-        rank[loc] = (int32_t)r;
-        longv[atomicAdd(&nlong, 1)] = loc;
+      sv[r] = (int32_t)v;
+    }
+  }
+}
+
+// CO[mu] is the prefix of ranks [0, |CO[mu]|) (ranks are degree-descending),
+// and vertex v's entry in CO[mu] is no_sim[off[v] + mu - 2]. So the core order
+// is a transpose of the neighbour-order rows taken in rank order: a tile of
+// kFillRanks consecutive ranks x kFillMu consecutive mu is read row-contiguously
+// into LDS and written segment-contiguously.
+constexpr int kFillRanks = 64;
+constexpr int kFillMu = 32;
+
+__global__ void k_co_tiles(const int32_t *sv, const int32_t *deg, int64_t nz, int32_t *tiles_of) {
+  const int64_t nt = (nz + kFillRanks - 1) / kFillRanks;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
+       t += (int64_t)gridDim.x * blockDim.x)
+    tiles_of[t] = (deg[sv[t * kFillRanks]] + kFillMu - 1) / kFillMu;  // first rank has the top degree
+}
+
+__global__ __launch_bounds__(256) void k_co_fill(const int32_t *sv, const int32_t *deg,
+                                                 const int64_t *off, const double *no_sim,
+                                                 const int64_t *co_off, int64_t nz,
+                                                 const int64_t *tile_first, int64_t nrt,
+                                                 double *co_key, int32_t *co_id) {
+  __shared__ double tile[kFillMu][kFillRanks + 1];
+  __shared__ int32_t vs[kFillRanks], vd[kFillRanks];
+  __shared__ int64_t vo[kFillRanks];
+  __shared__ int64_t s_t, s_k;
+  const int64_t total = tile_first[nrt];
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t lo = 0, hi = nrt;  // last t with tile_first[t] <= b
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (tile_first[mid] <= b) lo = mid;
+        else hi = mid;
       }
+      s_t = lo;
+      s_k = b - tile_first[lo];
     }
     __syncthreads();
-    for (int i = wave; i < nlong; i += blockDim.x / kWave) {
-      const int loc = longv[i];
-      const int64_t v = t0 + loc;
-      const int32_t d = deg[v];
-      const int64_t r = rank[loc];
-      const int64_t o = off[v];
-      for (int32_t j = lane; j < d; j += kWave) {
-        const int64_t pos = co_off[j + 2] + r;
-        co_key[pos] = no_sim[o + j];
-        co_id[pos] = (int32_t)v;
+    const int64_t r0 = s_t * kFillRanks;
+    const int32_t j0 = (int32_t)(s_k * kFillMu);
+    if (threadIdx.x < kFillRanks) {
+      const int64_t r = r0 + threadIdx.x;
+      int32_t v = 0, d = 0;
+      int64_t o = 0;
+      if (r < nz) {
+        v = sv[r];
+        d = deg[v];
+        o = off[v];
+      }
+      vs[threadIdx.x] = v;
+      vd[threadIdx.x] = d;
+      vo[threadIdx.x] = o;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kFillRanks * kFillMu; e += blockDim.x) {
+      const int i = e / kFillMu, j = e % kFillMu;
+      if (j0 + j < vd[i]) tile[j][i] = no_sim[vo[i] + j0 + j];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kFillRanks * kFillMu; e += blockDim.x) {
+      const int j = e / kFillRanks, i = e % kFillRanks;
+      if (j0 + j < vd[i]) {
+        const int64_t pos = co_off[j0 + j + 2] + r0 + i;
+        co_key[pos] = tile[j][i];
+        co_id[pos] = vs[i];
       }
     }
   }
@@ -409,8 +448,23 @@ scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStre
   k_co_sizes<<<grid_for(dmax, 256), 256, 0, s>>>(E, n, dmax, sizes);
   BTRY(exclusive_scan64(sizes, co_scan, dmax, scan_ws, s));
   k_co_finish_off<<<grid_for(dmax + 3, 256), 256, 0, s>>>(co_scan, dmax, ix->co_off);
-  k_co_place<<<grid_for(n, kPlaceTile, 4096), 256, 0, s>>>(ix->off, deg, n, dmax, E, cursor, ix->co_off,
-                                                           ix->no_sim, co_key, co_id);
+  int32_t *sv, *tiles_of;
+  int64_t *tile_first;
+  const int64_t nrt_max = (n + kFillRanks - 1) / kFillRanks;
+  BTRY(tmp.alloc(&sv, n));
+  BTRY(tmp.alloc(&tiles_of, nrt_max));
+  BTRY(tmp.alloc(&tile_first, nrt_max + 1));
+  k_co_rank<<<grid_for(n, kRankTile, 4096), 256, 0, s>>>(deg, n, dmax, E, cursor, sv);
+  // nz = |CO[2]| = number of non-isolated vertices = co_off[3] - co_off[2]
+  int64_t co23[2];
+  BHIP(hipMemcpyAsync(co23, ix->co_off + 2, 16, hipMemcpyDeviceToHost, s));
+  BHIP(hipStreamSynchronize(s));
+  const int64_t nz = co23[1] - co23[0];
+  const int64_t nrt = (nz + kFillRanks - 1) / kFillRanks;
+  k_co_tiles<<<grid_for(nrt, 256), 256, 0, s>>>(sv, deg, nz, tiles_of);
+  BTRY(exclusive_scan(tiles_of, tile_first, nrt, scan_ws, s));
+  k_co_fill<<<grid_for(nnz / 512 + 1, 1, 1 << 16), 256, 0, s>>>(sv, deg, ix->off, ix->no_sim, ix->co_off, nz,
+                                                                tile_first, nrt, co_key, co_id);
   BTRY(segmented_sort(ix->co_off + 2, dmax, nnz, co_key, co_id, ix->co_thr, ix->co_ids, s));
   mark(5);
   BHIP(hipGetLastError());

@@ -47,6 +47,18 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ int32_t wave_sum(int32_t v) {
+#pragma unroll
+  for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int m = kWave / 2; m > 0; m >>= 1) v = max(v, __shfl_xor(v, m, kWave));
+  return v;
+}
+
 __device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
   const int lane = lane_id();
 #pragma unroll
@@ -184,13 +196,15 @@ __global__ __launch_bounds__(64) void k_small_owner(const int32_t *list, int32_t
 // Big owners: persistent workgroups with an LDS bitmap window.
 
 constexpr int kBigThreads = 1024;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;   // loads in flight per lane
+constexpr int kSeg = 1024;   // ids per work item (rows longer than this are split)
 
 struct BigShared {
   int32_t chunk;
   int32_t nlow;
   int32_t next;
-  int32_t pad;
+  int32_t nextra;
+  int32_t wsum[kBigThreads / kWave];
 };
 
 // First position in row[lo, hi) whose id is >= key, searched 64-wide by the
@@ -215,6 +229,31 @@ __device__ __forceinline__ int64_t wave_lower_bound(const int32_t *row, int64_t 
   return lo + __popcll(__ballot(less));
 }
 
+// Exclusive prefix sum over the workgroup (one value per thread, up to 1024
+// threads); *total receives the sum. wsum holds one int per wavefront.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int32_t *total) {
+  const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int32_t incl = wave_incl_sum(v);
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    const int32_t w = lane < nw ? wsum[lane] : 0;
+    const int32_t wi = wave_incl_sum(w);
+    if (lane < nw) wsum[lane] = wi - w;
+    if (lane == nw - 1) *total = wi;
+  }
+  __syncthreads();
+  return incl - v + wsum[wave];
+}
+
+// One workgroup per chunk (owner h, up to spc row slots), persistent over a
+// global chunk counter. Per id window: the owner's ids in the window are set
+// in the LDS bitmap; each lower neighbour's ids in the window are cut into
+// segments of kSeg ids, and wavefronts claim segments from an LDS counter
+// (item j < nlow is the first segment of edge j; later items are the extra
+// segments of long rows), so one long row cannot hold the workgroup at the
+// barrier that ends the window. Partial counts meet in LDS.
+template <bool kOneWindow>
 __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     const BigChunk *chunks, int32_t nchunks, PlanCounts *pc, int spc, int wbits, int64_t n,
     const int64_t *off, const int32_t *deg, const int32_t *adj, int kind, double *sims,
@@ -226,13 +265,14 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
   int64_t *le_ou = (int64_t *)(bm + nwords);
   int64_t *le_mir = le_ou + spc;
   int32_t *le_e = (int32_t *)(le_mir + spc);
-  int32_t *le_u = le_e + spc;
-  int32_t *le_du = le_u + spc;
+  int32_t *le_du = le_e + spc;
   int32_t *le_cnt = le_du + spc;
-  int32_t *le_cur = le_cnt + spc;
-  BigShared *sh = (BigShared *)(le_cur + spc);
+  int32_t *le_b0 = le_cnt + spc;
+  int32_t *le_b1 = le_b0 + spc;  // end of the range in the current window (cursor)
+  int32_t *le_xp = le_b1 + spc;  // [spc + 1] exclusive prefix of extra segments
+  BigShared *sh = (BigShared *)(le_xp + spc + 1);
   const int tid = threadIdx.x, lane = lane_id();
-  const bool one_window = n <= W;
+  constexpr bool one_window = kOneWindow;  // the whole id space fits one window
 
   for (int i = tid; i < nwords; i += blockDim.x) bm[i] = 0u;
   for (;;) {
@@ -269,12 +309,12 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       if (low) {
         const int k = base + __popcll(mk & lanes_below());
         le_e[k] = e;
-        le_u[k] = u;
         le_du[k] = du;
         le_ou[k] = off[u];
         le_cnt[k] = 0;
         le_mir[k] = -1;
-        le_cur[k] = 0;
+        le_b0[k] = 0;
+        le_b1[k] = one_window ? du : 0;
       }
     }
     __syncthreads();
@@ -289,45 +329,122 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         const int32_t x = (int32_t)(adj[oh + i] - w0);
         atomicOr(&bm[x >> 5], 1u << (x & 31));
       }
+      if (!one_window) {
+        // each lower neighbour's ids inside this window, after the last one
+        if (tid == 0) sh->next = 0;
+        __syncthreads();
+        for (;;) {
+          const int32_t i = uniform(atomicAdd(&sh->next, lane == 0 ? 1 : 0));
+          if (i >= nlow) break;
+          const int32_t du = uniform(le_du[i]);
+          const int32_t *row = adj + uniform64(le_ou[i]);
+          const int64_t b0 = wave_lower_bound(row, uniform(le_b1[i]), du, (int32_t)w0);
+          const int64_t b1 = wave_lower_bound(row, b0, du, (int32_t)min(w0 + W, (int64_t)INT32_MAX));
+          le_b0[i] = (int32_t)b0;
+          le_b1[i] = (int32_t)b1;
+        }
+        __syncthreads();
+      }
+      // Extra segments of long ranges, as an exclusive prefix over the edges.
+      int32_t ex = 0;
+      if (tid < nlow) {
+        const int32_t len = le_b1[tid] - le_b0[tid];
+        ex = len > kSeg ? (len - 1) / kSeg : 0;
+      }
+      const int32_t xp = block_excl_scan(ex, sh->wsum, &sh->nextra);
+      if (tid < nlow) le_xp[tid] = xp;
       if (tid == 0) sh->next = 0;
       __syncthreads();
-      for (;;) {
-        // Every lane takes part in the claim (lane 0 adds 1, the others 0) so
-        // the loop has no lane-dependent branch; lane 0's result is the claim.
-        const int32_t i = uniform(atomicAdd(&sh->next, lane == 0 ? 1 : 0));
-        if (i >= nlow) break;
-        const int32_t du = uniform(le_du[i]);
-        const int64_t ou = uniform64(le_ou[i]);
-        int64_t b0 = 0, b1 = du;
-        if (!one_window) {
-          // ids of N(u) inside [w0, w0 + W): resume after the previous window
-          b0 = wave_lower_bound(adj + ou, uniform(le_cur[i]), du, (int32_t)w0);
-          b1 = wave_lower_bound(adj + ou, b0, du, (int32_t)min(w0 + W, (int64_t)INT32_MAX));
+      const int32_t nitems = nlow + uniform(sh->nextra);
+      // Software pipeline over work items: the next item is claimed and its
+      // first kWave*kUnroll ids are requested before the current item's ids
+      // are probed, so two items' loads are in flight per wavefront.
+      auto claim = [&](int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou) {
+        const int32_t j = uniform(atomicAdd(&sh->next, lane == 0 ? 1 : 0));
+        if (j >= nitems) {
+          e = -1;
+          lo = hi = 0;
+          ou = 0;
+          return;
         }
-        int32_t t = 0;
-        int64_t mpos = -1;
-        for (int64_t base = b0; base < b1; base += kWave * kUnroll) {
+        int32_t ee = j, sg = 0;
+        if (j >= nlow) {
+          const int32_t jj = j - nlow;
+          int32_t a0 = 0, a1 = nlow;  // last edge with le_xp[e] <= jj
+          while (a1 - a0 > 1) {
+            const int32_t mid = (a0 + a1) >> 1;
+            if (uniform(le_xp[mid]) <= jj) a0 = mid;
+            else a1 = mid;
+          }
+          ee = a0;
+          sg = 1 + jj - uniform(le_xp[a0]);
+        }
+        e = ee;
+        ou = uniform64(le_ou[ee]);
+        lo = uniform(le_b0[ee]) + sg * kSeg;
+        hi = min(uniform(le_b1[ee]), lo + kSeg);
+      };
+      // Branch-free loads (a lane past the end reads adj[0] and discards it)
+      // keep the loads unconditional, so the compiler waits only for the ones
+      // it consumes.
+      // Loads are branch-free (a lane past the end re-reads the row's first
+      // id and discards it) and their values are only read by the probe, so
+      // the compiler waits only for the loads it consumes. Hits and the
+      // position of h are kept per lane and reduced once per item.
+      // Validity is applied with masks, not branches (mask = all ones for a
+      // lane inside the item, zero past its end).
+      auto fetch = [&](int32_t x[kUnroll], const int32_t *row, uint32_t base, uint32_t hi) {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          const uint32_t q = base + k * kWave + lane;
+          const uint32_t vm = 0u - (uint32_t)(q < hi);
+          x[k] = row[q & vm];
+        }
+      };
+      auto probe = [&](const int32_t x[kUnroll], uint32_t base, uint32_t hi, int32_t &cnt,
+                       int32_t &mpi) {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          const uint32_t q = base + k * kWave + lane;
+          const uint32_t vb = (uint32_t)(q < hi);
+          const uint32_t vm = 0u - vb;
+          // inside [lo, hi) every id lies in the current window
+          const uint32_t y = kOneWindow ? (uint32_t)x[k] : (uint32_t)(x[k] - (int32_t)w0);
+          const uint32_t word = bm[(y >> 5) & vm];
+          cnt += (int32_t)((word >> (y & 31u)) & vb);
+          const uint32_t eq = (uint32_t)(x[k] == h) & vb;
+          mpi = eq ? (int32_t)q : mpi;
+        }
+      };
+      int32_t ea, loa, hia;
+      int64_t oua;
+      int32_t xa[kUnroll];
+      claim(ea, loa, hia, oua);
+      fetch(xa, adj + oua, (uint32_t)loa, (uint32_t)hia);
+      while (ea >= 0) {
+        int32_t eb, lob, hib;
+        int64_t oub;
+        int32_t xb[kUnroll];
+        claim(eb, lob, hib, oub);
+        fetch(xb, adj + oub, (uint32_t)lob, (uint32_t)hib);
+        int32_t cnt = 0, mpi = -1;
+        probe(xa, (uint32_t)loa, (uint32_t)hia, cnt, mpi);
+        for (int32_t base = loa + kWave * kUnroll; base < hia; base += kWave * kUnroll) {
           int32_t x[kUnroll];
-#pragma unroll
-          for (int k = 0; k < kUnroll; ++k) {
-            const int64_t q = base + k * kWave + lane;
-            x[k] = q < b1 ? adj[ou + q] : -1;
-          }
-#pragma unroll
-          for (int k = 0; k < kUnroll; ++k) {
-            bool hit = false;
-            const int64_t y = (int64_t)x[k] - w0;
-            if (x[k] >= 0 && y >= 0 && y < W) hit = (bm[y >> 5] >> (y & 31)) & 1u;
-            t += __popcll(__ballot(hit));
-            const uint64_t me = __ballot(x[k] == h);
-            if (me) mpos = ou + base + k * kWave + (__ffsll((unsigned long long)me) - 1);
-          }
+          fetch(x, adj + oua, (uint32_t)base, (uint32_t)hia);
+          probe(x, (uint32_t)base, (uint32_t)hia, cnt, mpi);
         }
-        // t, mpos and b1 are wave-uniform: every lane stores the same values.
-        const int32_t cnt_i = uniform(le_cnt[i]);
-        le_cnt[i] = cnt_i + t;
-        if (mpos >= 0) le_mir[i] = mpos;
-        le_cur[i] = (int32_t)b1;
+        const int32_t t = wave_sum(cnt);
+        const int32_t mp = wave_max(mpi);
+        // t and mp are wave-uniform; lane 0 adds, every lane stores the mirror.
+        atomicAdd(&le_cnt[ea], lane == 0 ? t : 0);
+        if (mp >= 0) le_mir[ea] = oua + mp;
+        ea = eb;
+        loa = lob;
+        hia = hib;
+        oua = oub;
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) xa[k] = xb[k];
       }
       __syncthreads();
       for (int64_t i = p + tid; i < pe; i += blockDim.x) {
@@ -359,7 +476,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
 // Host side.
 
 static size_t big_lds_bytes(int wbits, int spc) {
-  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 8 + 4 * 5) + sizeof(BigShared);
+  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 8 + 4 * 6) + 4 + sizeof(BigShared);
 }
 
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
@@ -405,13 +522,18 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   }
   if (h.big) {
     size_t lds = big_lds_bytes(wbits, cfg.spc);
+    const bool one = n <= ((int64_t)1 << wbits);
+    const void *fn = one ? (const void *)k_big_owner<true> : (const void *)k_big_owner<false>;
     if (lds > 65536)
-      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_big_owner,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      SCAN_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (size_t)lds_max / lds));
     int grid = std::min<int64_t>((int64_t)cus * per_cu, h.big);
-    k_big_owner<<<grid, kBigThreads, lds, s>>>(big_list, h.big, pc, cfg.spc, wbits, n, off, deg,
-                                               adj, kind, sims, counts);
+    if (one)
+      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, h.big, pc, cfg.spc, wbits, n, off,
+                                                       deg, adj, kind, sims, counts);
+    else
+      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, h.big, pc, cfg.spc, wbits, n, off,
+                                                        deg, adj, kind, sims, counts);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);
