@@ -262,31 +262,26 @@ scan_status scan_index_export(const scan_index *ix, scan_array what, void *host_
 
 scan_status scan_index_build_profile(const scan_index *ix, scan_build_profile *out) {
   if (!ix || !out) return fail(SCAN_EINVAL, "null argument");
-  if (!(ix->flags & SCAN_PROFILE) || !ix->ev[0]) return fail(SCAN_EINVAL, "index was built without SCAN_PROFILE");
-  SCAN_HIP_TRY(hipEventSynchronize(ix->ev[5]));
+  if (!ix->prof || !ix->prof->ev[0]) return fail(SCAN_EINVAL, "index was built without SCAN_PROFILE");
+  const auto &ev = ix->prof->ev;
+  SCAN_HIP_TRY(hipEventSynchronize(ev[5]));
   float t[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = 1; k < 6; ++k) SCAN_HIP_TRY(hipEventElapsedTime(&t[k], ix->ev[k - 1], ix->ev[k]));
+  for (int k = 1; k < 6; ++k) SCAN_HIP_TRY(hipEventElapsedTime(&t[k], ev[k - 1], ev[k]));
   float total = 0;
-  SCAN_HIP_TRY(hipEventElapsedTime(&total, ix->ev[0], ix->ev[5]));
+  SCAN_HIP_TRY(hipEventElapsedTime(&total, ev[0], ev[5]));
   out->total_ms = total;
   out->prepare_ms = t[1];
   out->plan_ms = t[2];
   out->intersect_ms = t[3];
   out->no_sort_ms = t[4];
   out->core_order_ms = t[5];
-  out->intersect_launches = ix->intersect_launches;
-  out->owners = ix->owners;
+  out->intersect_launches = ix->prof->intersect_launches;
+  out->owners = ix->prof->owners;
   return SCAN_OK;
 }
 
 void scan_index_free(scan_index *ix) {
   if (!ix) return;
-  for (auto &e : ix->ev)
-    if (e) {
-      (void)hipEventSynchronize(e);
-      (void)hipEventDestroy(e);
-      e = nullptr;
-    }
   {
     std::lock_guard<std::mutex> lk(ix->pool_mu);
     for (auto *p : ix->pool) {

@@ -1,6 +1,7 @@
 // Index object and internal entry points shared by the library's host code.
 #pragma once
 
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -41,6 +42,33 @@ struct QueryDesc;  // device-side query descriptor (query.hip)
 
 }  // namespace scan
 
+namespace scan {
+
+struct DevAlloc {
+  void *p;
+  size_t bytes;
+};
+
+// Device buffers shared by the indexes of one batched build (each index is a
+// view into them); freed when the last index referring to it is freed.
+struct SharedArena {
+  hipStream_t stream = nullptr;
+  std::vector<DevAlloc> allocs;
+  int64_t bytes = 0;
+  ~SharedArena();
+};
+
+// SCAN_PROFILE events of a build (shared by the indexes of a batch): start,
+// prepare, plan, intersect, neighbour order, core order.
+struct BuildProfileEvents {
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t intersect_launches = 0;
+  int32_t owners = 0;
+  ~BuildProfileEvents();
+};
+
+}  // namespace scan
+
 struct scan_index {
   int64_t n = 0, nnz = 0, dmax = 0;
   int32_t kind = 0;
@@ -55,17 +83,9 @@ struct scan_index {
   double *co_thr = nullptr;    // double[nnz]
   double *sims = nullptr;      // double[nnz] (SCAN_KEEP_SIMS)
   int32_t *counts = nullptr;   // int32[nnz]  (SCAN_KEEP_COUNTS)
-  struct Alloc {
-    void *p;
-    size_t bytes;
-  };
-  std::vector<Alloc> allocs;
-  // SCAN_PROFILE: events at phase boundaries (start, prepare, plan,
-  // intersect, neighbour order, core order).
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  int32_t intersect_launches = 0;
-  int32_t owners = 0;
-  int64_t bytes = 0;
+  std::shared_ptr<scan::SharedArena> arena;        // owns the arrays above
+  std::shared_ptr<scan::BuildProfileEvents> prof;  // SCAN_PROFILE only
+  int64_t bytes = 0;                               // device bytes of this index's arrays
   // Query workspace pool: a slot may be reused once its last use completed
   // (event) or when the new use is on the same stream.
   struct PooledSlot {
@@ -80,7 +100,6 @@ struct scan_index {
 
 namespace scan {
 
-scan_status index_alloc(scan_index *ix, void **p, size_t bytes);
 void index_release(scan_index *ix);
 
 scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStream_t stream,
