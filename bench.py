@@ -44,6 +44,64 @@ def byte_model(st: dict, s_off: int) -> dict:
     return {"intersect": intersect, "build": build, "floor": floor}
 
 
+def serve_ladder(scan, torch, ix, n, mode, max_slots, max_batch, queries, rates, slo_ms, seed=11):
+    """Open-loop serving: `queries` requests with Poisson arrivals at each
+    offered rate, mu ~ U{2..16}, eps ~ U{0.10, 0.15, ..., 0.90}; results stay
+    in HBM (a ring of device result arrays). Latency = arrival -> result in
+    place, including time spent waiting to be admitted. Stops once the server
+    no longer keeps up."""
+    import time as _t
+
+    rng = np.random.default_rng(seed)
+    mu = rng.integers(2, 17, queries).astype(np.int32)
+    eps = np.array([(10 + 5 * k) / 100.0 for k in rng.integers(0, 17, queries)])
+    ring = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(64)]
+    owner = [0] * len(ring)
+    srv = scan.Server(ix, max_slots=max_slots, max_batch=max_batch, memory_budget=8 << 30, use_graph=True)
+    out = []
+    try:
+        for i in range(100):  # warm-up
+            srv.wait(srv.submit_ex(int(mu[i]), float(eps[i]), ring[i % len(ring)]))
+        for rate in rates:
+            gaps = rng.exponential(1.0 / rate, queries)
+            arrive = np.cumsum(gaps)
+            lat = np.zeros(queries)
+            lag = np.zeros(queries)
+            tickets = [0] * queries
+            t0 = _t.perf_counter()
+            for i in range(queries):
+                target = t0 + arrive[i]
+                while _t.perf_counter() < target:
+                    pass
+                r = i % len(ring)
+                if owner[r]:
+                    srv.wait(owner[r])
+                while True:
+                    t = srv.submit_ex(int(mu[i]), float(eps[i]), ring[r], lat.ctypes.data + 8 * i, block=False)
+                    if t is not None:
+                        break
+                lag[i] = (_t.perf_counter() - target) * 1e3
+                tickets[i] = owner[r] = t
+            for t in tickets:
+                srv.wait(t)
+            span = _t.perf_counter() - t0
+            owner = [0] * len(ring)
+            total = lat + lag
+            row = {"offered_qps": rate, "achieved_qps": queries / span,
+                   "p50_ms": float(np.percentile(total, 50)), "p99_ms": float(np.percentile(total, 99))}
+            out.append(row)
+            log(f"serve {mode}: {row}")
+            if row["achieved_qps"] < 0.9 * rate or row["p99_ms"] > 50 * slo_ms:
+                break
+    finally:
+        srv.close()
+    ok = [r for r in out if r["p99_ms"] <= slo_ms and r["achieved_qps"] >= 0.9 * r["offered_qps"]]
+    best = max(ok, key=lambda r: r["achieved_qps"]) if ok else None
+    return {"max_slots": max_slots, "max_batch": max_batch, "ladder": out,
+            "max_qps_within_slo": best["achieved_qps"] if best else 0.0,
+            "p99_at_max_ms": best["p99_ms"] if best else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +112,10 @@ def main():
     ap.add_argument("--seed", type=int, default=20)
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--query-batch", type=int, default=25)
+    ap.add_argument("--serve-queries", type=int, default=20000)
+    ap.add_argument("--serve-batch", type=int, default=32)
+    ap.add_argument("--serve-slo-ms", type=float, default=2.0)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -165,6 +227,17 @@ def main():
     }
     log(f"queries: {query}")
 
+    serving = None
+    if not args.no_serve:
+        rates = [2500, 5000, 10000, 20000, 40000, 80000, 160000]
+        B = args.serve_batch
+        serving = {"queries_per_rate": args.serve_queries, "arrivals": "poisson", "mu": "U{2..16}",
+                   "eps": "U{0.10,0.15,...,0.90}", "results": "device (HBM)", "p99_slo_ms": args.serve_slo_ms,
+                   "one_at_a_time": serve_ladder(scan, torch, ix, g.n, "one_at_a_time", 1, 1,
+                                                 args.serve_queries, rates, args.serve_slo_ms),
+                   "batched": serve_ladder(scan, torch, ix, g.n, "batched", 4 * B, B,
+                                           args.serve_queries, rates, args.serve_slo_ms)}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -199,6 +272,7 @@ def main():
         "phases_ms": phases,
         "device_ms_per_step": dev_ms / args.steps,
         "query": query,
+        "serving": serving,
         "roofline": {"bound": "hbm", "kernel": "k_intersect (all degree-class launches of one build)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

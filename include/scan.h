@@ -199,32 +199,52 @@ scan_status scan_index_build_profile(const scan_index *ix, scan_build_profile *o
 void scan_index_free(scan_index *ix);
 
 /* ---- Serving: continuous batching of (mu, eps) queries ----------------
- * A server keeps one index resident and answers queries submitted from any
- * host thread. Requests that arrive while others run are admitted as query
- * slots and device memory free up, and join the next device batch; each
- * result is identical to scan_query's. */
+ * A server keeps one index resident and answers GS*-Query requests (Section
+ * 4.2) submitted from any host thread. Its device memory is split into
+ * max_slots / max_batch batch buffers of max_batch query slots each (fewer if
+ * memory_budget holds fewer slots: each takes about 9*n bytes). A launcher
+ * thread starts a device batch of up to max_batch queued requests whenever a
+ * buffer is free; requests that arrive meanwhile queue and join the next
+ * batch, so several batches run at once on their own streams. A completer
+ * thread copies each finished result to the caller's host array. Every
+ * result is identical to scan_query's for the same (mu, eps).
+ * The index must outlive the server and stay unmodified; create waits for
+ * the index's stream. */
 typedef struct {
-  int32_t max_slots;        /* concurrent queries in flight (>= 1)            */
-  int32_t max_batch;        /* queries per device batch (>= 1)                */
+  int32_t max_slots;        /* query slots over all batch buffers (>= 1)      */
+  int32_t max_batch;        /* queries per device batch (1..1024)             */
   int64_t memory_budget;    /* device bytes for query workspaces + outputs    */
   int32_t use_graph;        /* 1: replay a captured HIP graph per batch       */
 } scan_server_opts;
 
 typedef struct scan_server scan_server;
 
-/* Errors: SCAN_EINVAL (bad opts), SCAN_ENOMEM (budget below one slot). */
+/* Errors: SCAN_EINVAL (bad opts), SCAN_ENOMEM (budget below one slot or an
+ * allocation failed), SCAN_EDEVICE (stream, event or graph set-up failed). */
 scan_status scan_server_create(const scan_index *ix, const scan_server_opts *opts,
                                scan_server **out);
-/* Queues (mu, eps); the result is copied to host `dst` (int32[n]) when done.
- * SCAN_EBUSY when no slot is free within the memory budget (nothing queued),
- * SCAN_EINVAL for mu < 2 or NaN eps. *ticket identifies the request. */
+/* Queues (mu, eps); the memberships (int32[n], as scan_query's) are written
+ * to host `dst`, which must stay valid until the ticket completes.
+ * SCAN_EBUSY when the request queue (4 * slots, at least 64) is full: nothing
+ * is queued and the caller retries later. SCAN_EINVAL for mu < 2 or NaN eps.
+ * *ticket (> 0) identifies the request. */
 scan_status scan_server_submit(scan_server *s, int32_t mu, double eps, int32_t *dst,
                                uint64_t *ticket);
-/* *done = 1 once the result for ticket is in dst. */
+/* As scan_server_submit; dst_on_device = 1: dst is device memory (int32[n]
+ * on the index's device), written by the query kernels directly, with no
+ * host copy; the result is visible to any stream once the ticket completes.
+ * latency_ms (host, may be NULL) receives the time from this call until the
+ * result was in dst. */
+scan_status scan_server_submit_ex(scan_server *s, int32_t mu, double eps, int32_t *dst,
+                                  int32_t dst_on_device, double *latency_ms, uint64_t *ticket);
+/* *done = 1 once the result for ticket is in dst. A ticket that reported
+ * done is forgotten (later polls also report done). */
 scan_status scan_server_poll(scan_server *s, uint64_t ticket, int32_t *done);
-/* Blocks until the ticket completes. */
+/* Blocks until the ticket completes; returns SCAN_EDEVICE if a device batch
+ * failed since the server started. */
 scan_status scan_server_wait(scan_server *s, uint64_t ticket);
-/* Drains outstanding requests, then frees everything. NULL is a no-op. */
+/* Drains outstanding requests (their results are still delivered), joins the
+ * server threads, then frees everything. NULL is a no-op. */
 void scan_server_destroy(scan_server *s);
 
 /* Diagnostic: evaluates the device similarity function the build uses on

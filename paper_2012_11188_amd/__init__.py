@@ -71,7 +71,7 @@ EXPORTS = [
     "scan_set_allocator", "scan_build_index", "scan_build_index_batch", "scan_query",
     "scan_query_ex", "scan_query_batch", "scan_index_get_info", "scan_index_export",
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
-    "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
+    "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
     "scan_version", "scan_similarity_values", "scan_index_build_profile",
 ]
 
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "scan_index_free": ([vp], None),
         "scan_server_create": ([vp, P(_ServerOpts), P(vp)], i32),
         "scan_server_submit": ([vp, i32, f64, vp, P(u64)], i32),
+        "scan_server_submit_ex": ([vp, i32, f64, vp, i32, vp, P(u64)], i32),
         "scan_server_poll": ([vp, u64, P(i32)], i32),
         "scan_server_wait": ([vp, u64], i32),
         "scan_server_destroy": ([vp], None),
@@ -387,14 +388,45 @@ class Server:
         _check(lib.scan_server_create(ix._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
 
+    def _dst(self, dst: np.ndarray) -> int:
+        n = self.ix.info.n
+        if not (isinstance(dst, np.ndarray) and dst.dtype == np.int32 and dst.shape == (n,)
+                and dst.flags.c_contiguous and dst.flags.writeable):
+            raise ValueError(f"dst must be a writeable contiguous int32 array of shape ({n},)")
+        return dst.ctypes.data
+
     def submit(self, mu: int, eps: float, dst: np.ndarray) -> int:
+        """Queues (mu, eps); dst (int32[n], kept alive by the caller) receives the
+        memberships. Raises ScanError(SCAN_EBUSY) when the queue is full."""
         t = ctypes.c_uint64()
-        _check(load_library().scan_server_submit(self._h, int(mu), float(eps), dst.ctypes.data, ctypes.byref(t)))
+        _check(load_library().scan_server_submit(self._h, int(mu), float(eps), self._dst(dst), ctypes.byref(t)))
+        return t.value
+
+    def submit_ex(self, mu: int, eps: float, dst, latency_ms: int = 0, block: bool = True):
+        """Queues (mu, eps) with dst either a host int32[n] array or a device
+        int32 tensor of n elements (written in place by the kernels).
+        latency_ms is the address of a host float64 (0: none) that receives the
+        request's latency. With block=False returns None when the queue is full."""
+        if not isinstance(dst, np.ndarray):
+            torch = _torch()
+            if not (isinstance(dst, torch.Tensor) and dst.is_cuda and dst.dtype == torch.int32
+                    and dst.numel() == self.ix.info.n and dst.is_contiguous()):
+                raise ValueError("device dst must be a contiguous int32 CUDA tensor of n elements")
+            ptr, on_dev = dst.data_ptr(), 1
+        else:
+            ptr, on_dev = self._dst(dst), 0
+        t = ctypes.c_uint64()
+        st = load_library().scan_server_submit_ex(self._h, int(mu), float(eps), ptr, on_dev, latency_ms or None,
+                                                  ctypes.byref(t))
+        if st == SCAN_EBUSY and not block:
+            return None
+        _check(st)
         return t.value
 
     def try_submit(self, mu: int, eps: float, dst: np.ndarray):
+        """Like submit, but returns None when the queue is full."""
         t = ctypes.c_uint64()
-        st = load_library().scan_server_submit(self._h, int(mu), float(eps), dst.ctypes.data, ctypes.byref(t))
+        st = load_library().scan_server_submit(self._h, int(mu), float(eps), self._dst(dst), ctypes.byref(t))
         if st == SCAN_EBUSY:
             return None
         _check(st)

@@ -33,12 +33,23 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
 
 // Per-query device workspace (one slot of a batch).
 struct QuerySlot {
-  int32_t *parent = nullptr;  // int32[n] union-find parents (cores only)
-  uint8_t *flag = nullptr;    // uint8[n] candidate borders; all zero between queries
+  int32_t *parent = nullptr;  // int32[n] union-find parents (read for cores only)
+  uint8_t *flag = nullptr;    // uint8[n] state: 2 core, 1 candidate border; all zero between queries
   size_t bytes = 0;
 };
 
-struct QueryDesc;  // device-side query descriptor (query.hip)
+// Device-side descriptor of one query of a batch (query.hip).
+struct QueryDesc {
+  int32_t mu;
+  int32_t pad;
+  double eps;
+  int64_t base;  // co_off[mu] (0 if mu > dmax + 1)
+  int64_t K;     // number of cores
+  int32_t *parent;
+  uint8_t *flag;
+  int32_t *memb;  // nullptr: unused batch entry
+  uint8_t *is_core;
+};
 
 }  // namespace scan
 
@@ -115,6 +126,11 @@ scan_status run_queries(const scan_index *ix, int32_t count, const int32_t *mu, 
                         const QuerySlot *slots, hipStream_t s);
 
 scan_status alloc_query_slot(const scan_index *ix, QuerySlot *slot, hipStream_t s);
+
+// Enqueues the four query kernels for `count` device descriptors.
+void launch_query_kernels(const scan_index *ix, QueryDesc *d, int32_t count, hipStream_t s);
+QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,
+                          uint8_t *is_core);
 void free_query_slot(QuerySlot *slot, hipStream_t s);
 
 IntersectConfig default_config();

@@ -2,20 +2,24 @@
 // connectivity by union-find as in Section 6.2; border vertices by the
 // deterministic rule of Section 7.3.4).
 //
-// Per query, four grid-stride kernels over a batch (blockIdx.y = query):
+// Per query, five grid-stride kernels over a batch (blockIdx.y = query). A
+// byte per vertex (the slot's state array, all zero between queries) marks
+// cores (2) and candidate borders (1):
 //   a7  k_q_cores   K = length of the eps-prefix of CO[mu] (binary search);
-//                   parent[u] = u for the K cores
+//                   for the K cores: state = 2, parent = self
 //   a8+a9 k_q_union for each core u, scan the eps-prefix of NO[u]; a core
 //                   neighbour w is united with u (larger root hooked under the
 //                   smaller, so every root is its component's smallest id); a
-//                   non-core neighbour is flagged as a candidate border
+//                   non-core neighbour is marked as a candidate border
 //   a9  k_q_jump    parent[u] = find(u) for every core
-//   a10 k_q_output  memberships: cores -> root; flagged non-cores -> root of
+//   a10 k_q_output  memberships: cores -> root; marked non-cores -> root of
 //                   the first core in their own NO row (NO is sorted by sim
 //                   desc, id asc, so that is the most similar eps-similar core,
-//                   ties to the lower id); others -1. Clears the flags.
+//                   ties to the lower id); others -1. Clears border marks.
+//       k_q_reset   clears the core marks.
 // A vertex w is a core iff deg(w) >= mu-1 and NO_SIM[off[w] + mu - 2] >= eps,
-// which is exactly membership in the eps-prefix of CO[mu].
+// which is exactly membership in the eps-prefix of CO[mu] (the CO entry of w
+// for mu carries that same threshold value).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,17 +29,7 @@
 
 namespace scan {
 
-struct QueryDesc {
-  int32_t mu;
-  int32_t pad;
-  double eps;
-  int64_t base;  // co_off[mu] (0 if mu > dmax + 1)
-  int64_t K;     // number of cores
-  int32_t *parent;
-  uint8_t *flag;
-  int32_t *memb;
-  uint8_t *is_core;
-};
+constexpr uint8_t kCore = 2, kBorder = 1;
 
 struct IndexView {
   int64_t n, dmax;
@@ -47,15 +41,25 @@ struct IndexView {
   const double *co_thr;
 };
 
-__device__ __forceinline__ bool core_test(const IndexView &ix, int32_t w, int32_t mu, double eps) {
-  int64_t o = ix.off[w];
-  int64_t d = ix.off[w + 1] - o;
-  return d >= (int64_t)mu - 1 && ix.no_sim[o + mu - 2] >= eps;
+// Length of the eps-prefix of CO[mu] (thresholds are sorted descending).
+__device__ __forceinline__ void core_prefix(const IndexView &ix, int32_t mu, double eps, int64_t &base,
+                                            int64_t &K) {
+  K = 0;
+  base = 0;
+  if ((int64_t)mu > ix.dmax + 1) return;
+  base = ix.co_off[mu];
+  int64_t lo = 0, hi = ix.co_off[mu + 1] - base;
+  while (lo < hi) {  // first position with thr < eps
+    int64_t mid = (lo + hi) >> 1;
+    if (ix.co_thr[base + mid] >= eps) lo = mid + 1;
+    else hi = mid;
+  }
+  K = lo;
 }
 
-// parent[] is reset to the identity for every vertex before each query, so it
-// is always a forest (hooks go from a root to a smaller root, halving moves a
-// pointer to an ancestor); the step cap only guards against a corrupt index.
+// parent[] entries of the query's cores form a forest (hooks go from a root
+// to a smaller root, halving moves a pointer to an ancestor); the step cap
+// only guards against a corrupt index.
 __device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x) {
   int32_t cur = x;
   for (int guard = 0; guard < (1 << 26); ++guard) {
@@ -83,33 +87,36 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
   }
 }
 
+// A descriptor with memb == nullptr is an unused batch entry: every kernel
+// skips it.
 __global__ void k_q_cores(IndexView ix, QueryDesc *qd) {
   QueryDesc &q = qd[blockIdx.y];
-  // K by binary search (thread 0 of block 0 of this query's column); every
-  // parent entry starts as the identity.
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int64_t K = 0, base = 0;
-    if ((int64_t)q.mu <= ix.dmax + 1) {
-      base = ix.co_off[q.mu];
-      int64_t lo = 0, hi = ix.co_off[q.mu + 1] - base;
-      while (lo < hi) {  // first position with thr < eps
-        int64_t mid = (lo + hi) >> 1;
-        if (ix.co_thr[base + mid] >= q.eps) lo = mid + 1;
-        else hi = mid;
-      }
-      K = lo;
+  if (!q.memb) return;
+  __shared__ int64_t sh[2];
+  if (threadIdx.x == 0) {  // every block finds K itself (same addresses: cache hits)
+    int64_t base, K;
+    core_prefix(ix, q.mu, q.eps, base, K);
+    sh[0] = base;
+    sh[1] = K;
+    if (blockIdx.x == 0) {
+      q.K = K;
+      q.base = base;
     }
-    q.K = K;
-    q.base = base;
   }
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < ix.n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    q.parent[v] = (int32_t)v;
+  __syncthreads();
+  const int64_t base = sh[0], K = sh[1];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < K;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = ix.co_ids[base + i];
+    q.parent[u] = u;
+    q.flag[u] = kCore;
+  }
 }
 
 // One wavefront per core; lanes stride the eps-prefix of its NO row.
 __global__ void k_q_union(IndexView ix, const QueryDesc *qd) {
   const QueryDesc q = qd[blockIdx.y];
+  if (!q.memb) return;
   int lane = threadIdx.x & (kWave - 1);
   int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -121,10 +128,10 @@ __global__ void k_q_union(IndexView ix, const QueryDesc *qd) {
       bool in = k < e && ix.no_sim[k] >= q.eps;
       if (in) {
         int32_t x = ix.no_ids[k];
-        if (core_test(ix, x, q.mu, q.eps)) {
+        if (q.flag[x] == kCore) {
           if (x < u) uf_union(q.parent, u, x);
         } else {
-          q.flag[x] = 1;
+          q.flag[x] = kBorder;
         }
       }
       if (!__all(in)) break;  // the prefix ended inside this chunk
@@ -134,6 +141,7 @@ __global__ void k_q_union(IndexView ix, const QueryDesc *qd) {
 
 __global__ void k_q_jump(IndexView ix, const QueryDesc *qd) {
   const QueryDesc q = qd[blockIdx.y];
+  if (!q.memb) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q.K;
        i += (int64_t)gridDim.x * blockDim.x) {
     int32_t u = ix.co_ids[q.base + i];
@@ -141,28 +149,57 @@ __global__ void k_q_jump(IndexView ix, const QueryDesc *qd) {
   }
 }
 
+// Reads core marks of other vertices, so border marks (own vertex only) are
+// the only ones it clears.
 __global__ void k_q_output(IndexView ix, const QueryDesc *qd) {
   const QueryDesc q = qd[blockIdx.y];
+  if (!q.memb) return;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < ix.n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    bool core = q.K > 0 && core_test(ix, (int32_t)v, q.mu, q.eps);
+    const uint8_t st = q.flag[v];
     int32_t m = -1;
-    if (core) {
+    if (st == kCore) {
       m = q.parent[v];
-    } else if (q.flag[v]) {
+    } else if (st == kBorder) {
       q.flag[v] = 0;
       int64_t b = ix.off[v], e = ix.off[v + 1];
       for (int64_t k = b; k < e && ix.no_sim[k] >= q.eps; ++k) {
         int32_t x = ix.no_ids[k];
-        if (core_test(ix, x, q.mu, q.eps)) {
+        if (q.flag[x] == kCore) {
           m = q.parent[x];
           break;
         }
       }
     }
     q.memb[v] = m;
-    if (q.is_core) q.is_core[v] = core ? 1 : 0;
+    if (q.is_core) q.is_core[v] = st == kCore ? 1 : 0;
   }
+}
+
+__global__ void k_q_reset(IndexView ix, const QueryDesc *qd) {
+  const QueryDesc q = qd[blockIdx.y];
+  if (!q.memb) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q.K;
+       i += (int64_t)gridDim.x * blockDim.x)
+    q.flag[ix.co_ids[q.base + i]] = 0;
+}
+
+void launch_query_kernels(const scan_index *ix, QueryDesc *d, int32_t count, hipStream_t s) {
+  IndexView v{ix->n, ix->dmax, ix->off, ix->no_ids, ix->no_sim, ix->co_off, ix->co_ids, ix->co_thr};
+  int64_t n = ix->n > 0 ? ix->n : 1;
+  dim3 gc(grid_for(n, 256, 1024), count);
+  dim3 gu(grid_for(n * kWave, 256, 2048), count);
+  dim3 go(grid_for(n, 256, 2048), count);
+  k_q_cores<<<gc, 256, 0, s>>>(v, d);
+  k_q_union<<<gu, 256, 0, s>>>(v, d);
+  k_q_jump<<<gc, 256, 0, s>>>(v, d);
+  k_q_output<<<go, 256, 0, s>>>(v, d);
+  k_q_reset<<<gc, 256, 0, s>>>(v, d);
+}
+
+QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,
+                          uint8_t *is_core) {
+  return QueryDesc{mu, 0, eps, 0, 0, slot.parent, slot.flag, memb, is_core};
 }
 
 scan_status alloc_query_slot(const scan_index *ix, QuerySlot *slot, hipStream_t s) {
@@ -207,15 +244,7 @@ scan_status run_queries(const scan_index *ix, int32_t count, const int32_t *mu, 
   // before the host vector goes out of scope.
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(SCAN_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
-  IndexView v{ix->n, ix->dmax, ix->off, ix->no_ids, ix->no_sim, ix->co_off, ix->co_ids, ix->co_thr};
-  int64_t n = ix->n > 0 ? ix->n : 1;
-  dim3 gc(grid_for(n, 256, 1024), count);
-  dim3 gu(grid_for(n * kWave, 256, 2048), count);
-  dim3 go(grid_for(n, 256, 2048), count);
-  k_q_cores<<<gc, 256, 0, s>>>(v, d);
-  k_q_union<<<gu, 256, 0, s>>>(v, d);
-  k_q_jump<<<gc, 256, 0, s>>>(v, d);
-  k_q_output<<<go, 256, 0, s>>>(v, d);
+  launch_query_kernels(ix, d, count, s);
   e = hipGetLastError();
   dev_free(d, sizeof(QueryDesc) * count, s);
   if (e != hipSuccess) return fail(SCAN_EDEVICE, "query launch: %s", hipGetErrorString(e));
