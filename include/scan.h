@@ -155,6 +155,40 @@ scan_status scan_build_index(const scan_csr *g, scan_sim_kind kind, uint32_t fla
 scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_kind kind,
                                    uint32_t flags, void *stream, scan_index **outs);
 
+/* Shape parameters of the intersection kernels (Algorithm 1's per-edge
+ * intersections). Every setting gives the same index bit for bit; they only
+ * change speed. A zero field takes its default.
+ *   small_max  owners of degree <= small_max use one wavefront each, with
+ *              their row in LDS (1..4096; default 256)
+ *   spc        row slots per work chunk of a larger owner (1..1024; default
+ *              512)
+ *   wbits      LDS bitmap window of 2^wbits vertex ids for larger owners
+ *              (10..24; default 20); lowered to what LDS holds and to the id
+ *              space; when the ids span several windows each chunk sweeps the
+ *              windows that hold its owner's neighbours */
+typedef struct {
+  int32_t small_max;
+  int32_t spc;
+  int32_t wbits;
+  int32_t reserved;  /* must be 0 */
+} scan_tune;
+
+/* scan_build_index_batch with explicit intersection shapes (tune may be
+ * NULL: defaults). count = 1 builds a single graph. Errors as for
+ * scan_build_index_batch; SCAN_EINVAL for a field out of range. */
+scan_status scan_build_index_ex(const scan_csr *gs, int32_t count, scan_sim_kind kind,
+                                uint32_t flags, const scan_tune *tune, void *stream,
+                                scan_index **outs);
+
+/* Autotuner: times the intersection phase of builds of gs (count graphs,
+ * merged as in scan_build_index_batch) over a coordinate sweep of scan_tune
+ * (small_max, then spc, then wbits; each candidate run `reps` times, the
+ * minimum kept) and writes the fastest setting to *best and its intersection
+ * time to *best_ms (may be NULL). Synchronous; builds and frees temporary
+ * indexes on `stream`. reps in 1..16. */
+scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind, int32_t reps,
+                          void *stream, scan_tune *best, float *best_ms);
+
 /* Clustering query (mu, eps), Algorithms 3-5 of Section 4.2 with the border
  * rule of Section 7.3.4. memberships: DEVICE pointer to int32[n]. Runs on the
  * stream the index was built on; asynchronous.

@@ -58,6 +58,11 @@ class _Profile(ctypes.Structure):
                 ("owners", ctypes.c_int32)]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [("small_max", ctypes.c_int32), ("spc", ctypes.c_int32), ("wbits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("memory_budget", ctypes.c_int64), ("use_graph", ctypes.c_int32)]
@@ -72,7 +77,8 @@ EXPORTS = [
     "scan_query_ex", "scan_query_batch", "scan_index_get_info", "scan_index_export",
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
-    "scan_version", "scan_similarity_values", "scan_index_build_profile",
+    "scan_version", "scan_similarity_values", "scan_index_build_profile", "scan_build_index_ex",
+    "scan_autotune",
 ]
 
 _lib = None
@@ -93,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         "scan_set_allocator": ([_ALLOC_FN, _RELEASE_FN, vp], i32),
         "scan_build_index": ([P(_Csr), i32, u32, vp, P(vp)], i32),
         "scan_build_index_batch": ([P(_Csr), i32, i32, u32, vp, P(vp)], i32),
+        "scan_build_index_ex": ([P(_Csr), i32, i32, u32, P(_Tune), vp, P(vp)], i32),
+        "scan_autotune": ([P(_Csr), i32, i32, i32, vp, P(_Tune), P(ctypes.c_float)], i32),
         "scan_query": ([vp, i32, f64, vp], i32),
         "scan_query_ex": ([vp, i32, f64, vp, vp, i32, vp], i32),
         "scan_query_batch": ([vp, i32, vp, vp, vp, i32, vp], i32),
@@ -247,8 +255,21 @@ def _csr_struct(off, adj):
     return c, (off, adj)
 
 
-def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None) -> Index:
-    """Builds the index (Algorithms 1 and 2) of the CSR graph (off, adj)."""
+def _tune_struct(tune):
+    """dict (small_max / spc / wbits; missing or 0 = default) -> scan_tune, or None."""
+    if tune is None:
+        return None
+    unknown = set(tune) - {"small_max", "spc", "wbits"}
+    if unknown:
+        raise ValueError(f"unknown tune fields {sorted(unknown)}")
+    return _Tune(int(tune.get("small_max", 0)), int(tune.get("spc", 0)), int(tune.get("wbits", 0)), 0)
+
+
+def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None, tune=None) -> Index:
+    """Builds the index (Algorithms 1 and 2) of the CSR graph (off, adj).
+    tune: optional intersection shapes {"small_max", "spc", "wbits"}."""
+    if tune is not None:
+        return scan_build_index_batch([(off, adj)], kind, flags, stream, tune)[0]
     lib = _ready()
     c, keep = _csr_struct(off, adj)
     s = _stream_handle(stream)
@@ -258,19 +279,41 @@ def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None) 
     return Index(out.value, s)
 
 
-def scan_build_index_batch(graphs, kind: int = COSINE, flags: int = 0, stream=None) -> list[Index]:
-    """Builds one index per (off, adj) graph in merged launches."""
-    lib = _ready()
+def _csr_array(graphs):
     structs, keep = [], []
     for off, adj in graphs:
         c, k = _csr_struct(off, adj)
         structs.append(c)
         keep.append(k)
-    arr = (_Csr * len(structs))(*structs)
-    outs = (ctypes.c_void_p * len(structs))()
+    return (_Csr * len(structs))(*structs), keep
+
+
+def scan_build_index_batch(graphs, kind: int = COSINE, flags: int = 0, stream=None, tune=None) -> list[Index]:
+    """Builds one index per (off, adj) graph in merged launches."""
+    lib = _ready()
+    arr, keep = _csr_array(graphs)
+    outs = (ctypes.c_void_p * len(arr))()
     s = _stream_handle(stream)
-    _check(lib.scan_build_index_batch(arr, len(structs), int(kind), int(flags), ctypes.c_void_p(s), outs))
-    return [Index(outs[i], s) for i in range(len(structs))]
+    t = _tune_struct(tune)
+    if t is None:
+        _check(lib.scan_build_index_batch(arr, len(arr), int(kind), int(flags), ctypes.c_void_p(s), outs))
+    else:
+        _check(lib.scan_build_index_ex(arr, len(arr), int(kind), int(flags), ctypes.byref(t), ctypes.c_void_p(s),
+                                       outs))
+    del keep
+    return [Index(outs[i], s) for i in range(len(arr))]
+
+
+def scan_autotune(graphs, kind: int = COSINE, reps: int = 2, stream=None) -> dict:
+    """Sweeps the intersection shapes on the (off, adj) graphs (built merged)
+    and returns {"small_max", "spc", "wbits", "ms"} of the fastest."""
+    lib = _ready()
+    arr, keep = _csr_array(graphs)
+    best, ms = _Tune(), ctypes.c_float()
+    _check(lib.scan_autotune(arr, len(arr), int(kind), int(reps), ctypes.c_void_p(_stream_handle(stream)),
+                             ctypes.byref(best), ctypes.byref(ms)))
+    del keep
+    return {"small_max": best.small_max, "spc": best.spc, "wbits": best.wbits, "ms": ms.value}
 
 
 def scan_index_get_info(ix: Index) -> IndexInfo:

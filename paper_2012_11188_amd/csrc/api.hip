@@ -2,7 +2,10 @@
 // index object's accessors and the query entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <initializer_list>
+#include <vector>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -180,6 +183,17 @@ static scan_status query_impl(const scan_index *cix, int32_t count, const int32_
   return st;
 }
 
+// Zero fields take the defaults; ranges are checked by the build.
+static scan_status tune_to_config(const scan_tune *t, IntersectConfig *c) {
+  *c = default_config();
+  if (!t) return SCAN_OK;
+  if (t->reserved != 0) return fail(SCAN_EINVAL, "scan_tune.reserved must be 0");
+  if (t->small_max) c->small_max = t->small_max;
+  if (t->spc) c->spc = t->spc;
+  if (t->wbits) c->wbits = t->wbits;
+  return SCAN_OK;
+}
+
 extern "C" {
 
 scan_status scan_set_allocator(scan_alloc_fn alloc, scan_release_fn release, void *ctx) {
@@ -203,6 +217,62 @@ scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_k
                                    uint32_t flags, void *stream, scan_index **outs) {
   return build_index_batch(gs, count, (int32_t)kind, flags, (hipStream_t)stream, default_config(),
                            outs);
+}
+
+scan_status scan_build_index_ex(const scan_csr *gs, int32_t count, scan_sim_kind kind, uint32_t flags,
+                                const scan_tune *tune, void *stream, scan_index **outs) {
+  IntersectConfig cfg;
+  SCAN_TRY(tune_to_config(tune, &cfg));
+  return build_index_batch(gs, count, (int32_t)kind, flags, (hipStream_t)stream, cfg, outs);
+}
+
+scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind, int32_t reps,
+                          void *stream, scan_tune *best, float *best_ms) {
+  if (!best || count < 1 || !gs) return fail(SCAN_EINVAL, "null argument or empty batch");
+  if (reps < 1 || reps > 16) return fail(SCAN_EINVAL, "reps must be in 1..16");
+  const hipStream_t s = (hipStream_t)stream;
+  std::vector<scan_index *> outs(count, nullptr);
+  // Plan + intersection time of one build with cfg (minimum over reps).
+  auto time_cfg = [&](const IntersectConfig &cfg, float *ms) -> scan_status {
+    float bt = INFINITY;
+    for (int32_t r = 0; r < reps; ++r) {
+      SCAN_TRY(build_index_batch(gs, count, (int32_t)kind, SCAN_PROFILE, s, cfg, outs.data()));
+      scan_build_profile prof;
+      const scan_status st = scan_index_build_profile(outs[0], &prof);
+      for (auto *&o : outs) {
+        scan_index_free(o);
+        o = nullptr;
+      }
+      SCAN_TRY(st);
+      bt = std::min(bt, (float)(prof.plan_ms + prof.intersect_ms));
+    }
+    *ms = bt;
+    return SCAN_OK;
+  };
+  IntersectConfig cur = default_config();
+  float cur_ms;
+  SCAN_TRY(time_cfg(cur, &cur_ms));
+  auto sweep = [&](int32_t IntersectConfig::*field, std::initializer_list<int32_t> values) -> scan_status {
+    const IntersectConfig base = cur;
+    for (int32_t v : values) {
+      if (base.*field == v) continue;
+      IntersectConfig c = base;
+      c.*field = v;
+      float ms;
+      SCAN_TRY(time_cfg(c, &ms));
+      if (ms < cur_ms) {
+        cur = c;
+        cur_ms = ms;
+      }
+    }
+    return SCAN_OK;
+  };
+  SCAN_TRY(sweep(&IntersectConfig::small_max, {32, 64, 128, 256, 512, 1024}));
+  SCAN_TRY(sweep(&IntersectConfig::spc, {128, 256, 512, 1024}));
+  SCAN_TRY(sweep(&IntersectConfig::wbits, {17, 18, 19, 20}));
+  *best = scan_tune{cur.small_max, cur.spc, cur.wbits, 0};
+  if (best_ms) *best_ms = cur_ms;
+  return SCAN_OK;
 }
 
 scan_status scan_query(const scan_index *ix, int32_t mu, double eps, int32_t *memberships) {

@@ -452,6 +452,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         bm[x >> 5] = 0u;
       }
       p = pe;
+      // the next window's bits may share words with the ones just cleared
+      if (!one_window) __syncthreads();
     }
     __syncthreads();
     for (int i = tid; i < nlow; i += blockDim.x) {
