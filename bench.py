@@ -1,20 +1,29 @@
-"""Benchmark: exact cosine SCAN index build on R-MAT scale 20 (edge factor 16,
-(a,b,c,d) = (.57,.19,.19,.05), symmetrised, deduplicated, self-loops removed,
-int32 CSR) on one MI355X, plus (mu, eps) query latency one at a time vs
-batched on the same index.
+"""Benchmark of the exact SCAN index build and (mu, eps) queries on one MI355X.
 
-One step = one full index build (degrees, ownership plan, intersection +
-FP64 similarity, neighbour order, core order) from a CSR resident in HBM to
-the index resident in HBM. Prints ONE JSON line on stdout; progress goes to
+Workloads (--workload):
+  rmat20 (default)  cosine index build on R-MAT scale 20 (edge factor 16,
+                    (a,b,c,d) = (.57,.19,.19,.05), symmetrised, deduplicated,
+                    self-loops removed, int32 CSR), with intersection shapes
+                    from the autotuner; then query latency one at a time vs
+                    batched on the same index, closed loop and as open-loop
+                    Poisson serving.
+  rmat23            cosine and Jaccard builds on R-MAT scale 23, edge factor
+                    32, int64 offsets (hubs of degree > 1e5).
+  sbm256            batched build of 256 uneven stochastic-block-model graphs:
+                    one merged build vs 256 per-graph builds.
+
+One step = one full index build (degrees, ownership plan, intersection + FP64
+similarity, neighbour order, core order) from a CSR resident in HBM to the
+index resident in HBM. Prints ONE JSON line on stdout; progress goes to
 stderr.
 
-  python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--scale 20]
-                  [--no-cpu-baseline] [--queries 200]
+  python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload rmat20]
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,36 +35,143 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+METRIC = "index-build edges/s (R-MAT-20); query p50/p99 ms, batched vs one-at-a-time"
+COUNTERS = os.path.join(ROOT, "profiles", "k_big_owner_rmat20_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2012_11188_amd", "csrc", "intersect.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def byte_model(st: dict, s_off: int) -> dict:
-    """Algorithmic bytes (fixed before measurement): CSR read once, W_min
-    shorter-row element reads plus one probe each (Algorithm 1's min-side
-    work), similarities written once per slot, neighbour-order and core-order
-    reads and writes."""
+def byte_model(st: dict, split: dict, s_off: int) -> dict:
+    """Algorithmic bytes, fixed before measurement. Build: CSR read once, the
+    min-side intersection work W_min (each shorter-row id read, 4 B, plus one
+    4 B probe), similarities written once per slot, neighbour order read and
+    written, core order read and written:
+        s_off(n+1) + 56 nnz + 8 W_min.
+    The bitmap-owner kernel alone: 8 W + 16 E over the edges it owns (W their
+    min-side work, E their count; each result goes to both CSR slots)."""
     n, nnz, wmin = st["n"], st["nnz"], st["w_min"]
-    intersect = s_off * (n + 1) + 4 * nnz + 8 * wmin + 8 * nnz
-    build = s_off * (n + 1) + 56 * nnz + 8 * wmin
-    floor = s_off * (n + 1) + 28 * nnz
-    return {"intersect": intersect, "build": build, "floor": floor}
+    return {
+        "build": s_off * (n + 1) + 56 * nnz + 8 * wmin,
+        "floor": s_off * (n + 1) + 28 * nnz,
+        "k_big_owner": 8 * split["w_big"] + 16 * split["edges_big"],
+        "k_small_owner": 8 * split["w_small"] + 16 * split["edges_small"],
+    }
 
 
-def serve_ladder(scan, torch, ix, n, mode, max_slots, max_batch, queries, rates, slo_ms, seed=11):
-    """Open-loop serving: `queries` requests with Poisson arrivals at each
-    offered rate, mu ~ U{2..16}, eps ~ U{0.10, 0.15, ..., 0.90}; results stay
-    in HBM (a ring of device result arrays). Latency = arrival -> result in
-    place, including time spent waiting to be admitted. Stops once the server
-    no longer keeps up."""
-    import time as _t
+def parse_tune(text: str):
+    if not text or text == "auto":
+        return None
+    if text == "default":
+        return {}
+    out = {}
+    for kv in text.split(","):
+        k, v = kv.split("=")
+        out[k.strip()] = int(v)
+    return out
 
+
+def tune_str(t: dict) -> str:
+    return f"small_max={t['small_max']} spc={t['spc']} wbits={t['wbits']}"
+
+
+def counter_traffic(tune: dict, workload: str):
+    """Measured HBM bytes per k_big_owner launch from the committed rocprofv3
+    counter summary, if it was taken on this kernel source, workload and
+    shape; else None and the reason."""
+    if not os.path.exists(COUNTERS):
+        return None, "no counter summary"
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != src:
+        return None, "kernel source changed since the counters were taken"
+    if kv.get("workload") != workload or kv.get("config") != tune_str(tune):
+        return None, f"counters taken on {kv.get('workload')} / {kv.get('config')}"
+    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
+    write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"])
+    return fetch + write, "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration"
+
+
+def timed_builds(scan, torch, build, steps: int, warmup: int):
+    """warmup untimed builds, then exactly `steps` builds back to back on the
+    current stream; returns wall ms/step, device ms/step, per-step profiles
+    and the last build's indexes."""
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        ixs = build()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {scan.scan_index_build_profile(ixs[0])}")
+        del ixs
+    profiles, keep = [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        keep.append(build())
+        if len(keep) > 1:
+            profiles.append(scan.scan_index_build_profile(keep.pop(0)[0]))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    profiles.append(scan.scan_index_build_profile(keep[-1][0]))
+    return wall * 1e3 / steps, ev0.elapsed_time(ev1) / steps, profiles, keep[-1]
+
+
+def med(profiles, key):
+    return float(np.median([p[key] for p in profiles]))
+
+
+PHASES = ("total_ms", "prepare_ms", "plan_ms", "intersect_ms", "intersect_small_ms", "intersect_big_ms",
+          "no_sort_ms", "core_order_ms")
+
+
+def autotune(scan, graphs, kind, tune_arg, reps=2):
+    """Returns (tune dict, info). --tune auto runs the autotuner (untimed)."""
+    t = parse_tune(tune_arg)
+    if t is not None:
+        full = {"small_max": t.get("small_max", 256), "spc": t.get("spc", 512), "wbits": t.get("wbits", 20)}
+        return full, {"source": "given"}
+    t0 = time.perf_counter()
+    best = scan.scan_autotune(graphs, kind, reps=reps)
+    info = {"source": "autotuner", "search_s": time.perf_counter() - t0, "intersect_ms": best["ms"]}
+    log(f"autotune: {best} in {info['search_s']:.1f}s")
+    return {k: best[k] for k in ("small_max", "spc", "wbits")}, info
+
+
+def kernel_roofline(bm, phases, tune, workload):
+    big_ms = phases["intersect_big_ms"]
+    achieved = bm["k_big_owner"] / (big_ms * 1e-3) / 1e9
+    traffic, why = counter_traffic(tune, workload)
+    return {"bound": "hbm", "kernel": "k_big_owner", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": why,
+            "bytes_per_launch": bm["k_big_owner"], "launch_ms": big_ms,
+            "traffic_over_algorithmic": (traffic / bm["k_big_owner"]) if traffic else None}
+
+
+# ---------------------------------------------------------------------------
+# Serving
+
+
+def serve_ladder(scan, torch, ix, n, mode, max_slots, max_batch, queries, rates, dst_kind, seed=11):
+    """Open-loop serving: `queries` requests with seeded Poisson arrivals at
+    each offered rate, mu ~ U{2..16}, eps ~ U{0.10, 0.15, ..., 0.90}. Results
+    go to a ring of device arrays or of pinned host arrays. Latency = result
+    in place minus scheduled arrival, including time spent waiting to be
+    admitted. Stops once the server no longer keeps up."""
     rng = np.random.default_rng(seed)
     mu = rng.integers(2, 17, queries).astype(np.int32)
     eps = np.array([(10 + 5 * k) / 100.0 for k in rng.integers(0, 17, queries)])
-    ring = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(64)]
+    if dst_kind == "device":
+        ring = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(64)]
+    else:
+        ring = [torch.empty(n, dtype=torch.int32).pin_memory().numpy() for _ in range(64)]
     owner = [0] * len(ring)
     srv = scan.Server(ix, max_slots=max_slots, max_batch=max_batch, memory_budget=8 << 30, use_graph=True)
     out = []
@@ -63,15 +179,14 @@ def serve_ladder(scan, torch, ix, n, mode, max_slots, max_batch, queries, rates,
         for i in range(100):  # warm-up
             srv.wait(srv.submit_ex(int(mu[i]), float(eps[i]), ring[i % len(ring)]))
         for rate in rates:
-            gaps = rng.exponential(1.0 / rate, queries)
-            arrive = np.cumsum(gaps)
+            arrive = np.cumsum(rng.exponential(1.0 / rate, queries))
             lat = np.zeros(queries)
             lag = np.zeros(queries)
             tickets = [0] * queries
-            t0 = _t.perf_counter()
+            t0 = time.perf_counter()
             for i in range(queries):
                 target = t0 + arrive[i]
-                while _t.perf_counter() < target:
+                while time.perf_counter() < target:
                     pass
                 r = i % len(ring)
                 if owner[r]:
@@ -80,26 +195,215 @@ def serve_ladder(scan, torch, ix, n, mode, max_slots, max_batch, queries, rates,
                     t = srv.submit_ex(int(mu[i]), float(eps[i]), ring[r], lat.ctypes.data + 8 * i, block=False)
                     if t is not None:
                         break
-                lag[i] = (_t.perf_counter() - target) * 1e3
+                lag[i] = (time.perf_counter() - target) * 1e3
                 tickets[i] = owner[r] = t
             for t in tickets:
                 srv.wait(t)
-            span = _t.perf_counter() - t0
+            span = time.perf_counter() - t0
             owner = [0] * len(ring)
             total = lat + lag
             row = {"offered_qps": rate, "achieved_qps": queries / span,
                    "p50_ms": float(np.percentile(total, 50)), "p99_ms": float(np.percentile(total, 99))}
             out.append(row)
-            log(f"serve {mode}: {row}")
-            if row["achieved_qps"] < 0.9 * rate or row["p99_ms"] > 50 * slo_ms:
+            log(f"serve {mode}/{dst_kind}: {row}")
+            if row["achieved_qps"] < 0.95 * rate:
                 break
     finally:
         srv.close()
-    ok = [r for r in out if r["p99_ms"] <= slo_ms and r["achieved_qps"] >= 0.9 * r["offered_qps"]]
-    best = max(ok, key=lambda r: r["achieved_qps"]) if ok else None
-    return {"max_slots": max_slots, "max_batch": max_batch, "ladder": out,
-            "max_qps_within_slo": best["achieved_qps"] if best else 0.0,
-            "p99_at_max_ms": best["p99_ms"] if best else None}
+    return {"max_slots": max_slots, "max_batch": max_batch, "ladder": out}
+
+
+def sustainable(ladder, p99_budget=None):
+    ok = [r for r in ladder if r["achieved_qps"] >= 0.95 * r["offered_qps"]
+          and (p99_budget is None or r["p99_ms"] <= p99_budget)]
+    return max(ok, key=lambda r: r["achieved_qps"]) if ok else None
+
+
+def serving(scan, torch, ix, n, args):
+    rates = [5000 * 1.5 ** k for k in range(9)]
+    B = args.serve_batch
+    res = {"queries_per_rate": args.serve_queries, "arrivals": "poisson (seeded, open loop)", "mu": "U{2..16}",
+           "eps": "U{0.10,0.15,...,0.90}", "use_graph": True}
+    for dst in ("device", "pinned_host"):
+        one = serve_ladder(scan, torch, ix, n, "one_at_a_time", 1, 1, args.serve_queries, rates, dst)
+        bat = serve_ladder(scan, torch, ix, n, "batched", 4 * B, B, args.serve_queries, rates, dst)
+        top = sustainable(one["ladder"])
+        budget = top["p99_ms"] if top else None
+        best = sustainable(bat["ladder"], budget) if budget else None
+        res[dst] = {"one_at_a_time": one, "batched": bat,
+                    "p99_budget_ms": budget,
+                    "one_at_a_time_max_qps": top["achieved_qps"] if top else 0.0,
+                    "batched_max_qps_within_budget": best["achieved_qps"] if best else 0.0}
+    return res
+
+
+def closed_loop_queries(scan, torch, ix, n, queries, B):
+    """mu ~ U{2..16}, eps ~ U{0.10, ..., 0.90}: synchronous one at a time vs
+    scan_query_batch of B."""
+    rng = np.random.default_rng(7)
+    q_mu = rng.integers(2, 17, queries)
+    q_eps = np.array([(10 + 5 * k) / 100.0 for k in rng.integers(0, 17, queries)])
+    memb = torch.empty(n, dtype=torch.int32, device="cuda")
+    for i in range(5):
+        scan.scan_query(ix, int(q_mu[i]), float(q_eps[i]), memb)
+    torch.cuda.synchronize()
+    single = []
+    for mu, eps in zip(q_mu, q_eps):
+        t = time.perf_counter()
+        scan.scan_query(ix, int(mu), float(eps), memb)
+        torch.cuda.synchronize()
+        single.append((time.perf_counter() - t) * 1e3)
+    out = torch.empty((B, n), dtype=torch.int32, device="cuda")
+    batched, tb0 = [], time.perf_counter()
+    for i in range(0, queries, B):
+        t = time.perf_counter()
+        scan.scan_query_batch(ix, q_mu[i:i + B], q_eps[i:i + B], out[: len(q_mu[i:i + B])])
+        torch.cuda.synchronize()
+        batched += [(time.perf_counter() - t) * 1e3] * len(q_mu[i:i + B])
+    tb = time.perf_counter() - tb0
+    return {"queries": queries, "batch": B,
+            "one_at_a_time": {"p50_ms": float(np.percentile(single, 50)), "p99_ms": float(np.percentile(single, 99)),
+                              "qps": queries / (sum(single) / 1e3)},
+            "batched": {"p50_ms": float(np.percentile(batched, 50)), "p99_ms": float(np.percentile(batched, 99)),
+                        "qps": queries / tb}}
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+
+
+def record(value, steps, warmup, ms, dtype, config, **extra):
+    rec = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    rec.update(extra)
+    return rec
+
+
+def rmat_workload(args, scan, torch, graphgen):
+    scale, ef = (20, 16) if args.workload == "rmat20" else (23, 32)
+    s_off = 4 if scale == 20 else 8
+    t0 = time.time()
+    g = graphgen.rmat(scale, ef, seed=scale)
+    st = graphgen.degree_stats(g)
+    log(f"graph rmat{scale}: n={g.n} |E|={g.num_edges} nnz={g.nnz} dmax={st['dmax']} w_min={st['w_min']} "
+        f"({time.time() - t0:.1f}s)")
+    off = torch.from_numpy(g.off.astype(np.int32 if s_off == 4 else np.int64)).cuda()
+    adj = torch.from_numpy(g.adj).cuda()
+    torch.cuda.synchronize()
+    kinds = [scan.COSINE] if scale == 20 else [scan.COSINE, scan.JACCARD]
+    tune, tinfo = autotune(scan, [(off, adj)], scan.COSINE, args.tune, reps=2 if scale == 20 else 1)
+    split = graphgen.owner_split(g, tune["small_max"])
+    bm = byte_model(st, split, s_off)
+    results = {}
+    for kind in kinds:
+        ms, dev_ms, profs, ixs = timed_builds(
+            scan, torch, lambda: [scan.scan_build_index(off, adj, kind, scan.SCAN_PROFILE, tune=tune)],
+            args.steps, args.warmup)
+        phases = {k: med(profs, k) for k in PHASES}
+        log(f"kind {kind}: {ms:.2f} ms/step wall, device {dev_ms:.2f} ms/step, phases {phases}")
+        results[kind] = (ms, dev_ms, phases, ixs[0])
+    ms, dev_ms, phases, ix = results[scan.COSINE]
+    value = g.num_edges / (ms * 1e-3)
+    workload = f"rmat{scale}_cosine_index_build"
+    config = {"workload": workload, "scale": scale, "edge_factor": ef, "abcd": [0.57, 0.19, 0.19, 0.05],
+              "seed": scale, "n": g.n, "edges": g.num_edges, "nnz": g.nnz, "dmax": st["dmax"],
+              "hubs_deg_gt_1e5": int((np.diff(g.off) > 100_000).sum()), "w_min": st["w_min"],
+              "offsets": "int32" if s_off == 4 else "int64", "ids": "int32", "similarity": "cosine",
+              "tune": tune}
+    extra = {"phases_ms": phases, "device_ms_per_step": dev_ms,
+             "tune": dict(tinfo, **tune), "owner_split": split,
+             "roofline": kernel_roofline(bm, phases, tune, workload),
+             "build_roofline": {"bytes": bm["build"], "floor_bytes": bm["floor"],
+                                "achieved": bm["build"] / (phases["total_ms"] * 1e-3) / 1e9,
+                                "frac": bm["build"] / (phases["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "floor_frac": bm["floor"] / (phases["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+             "k_small_owner": {"bytes": bm["k_small_owner"], "launch_ms": phases["intersect_small_ms"],
+                               "achieved_gbs": bm["k_small_owner"] / max(phases["intersect_small_ms"], 1e-6) / 1e6}}
+    if scan.JACCARD in results:
+        jms, jdev, jph, _ = results[scan.JACCARD]
+        extra["jaccard"] = {"value": g.num_edges / (jms * 1e-3), "ms_per_step": jms, "device_ms_per_step": jdev,
+                            "phases_ms": jph}
+    if scale == 20 and not args.no_queries:
+        extra["query"] = closed_loop_queries(scan, torch, ix, g.n, args.queries, args.query_batch)
+        log(f"queries: {extra['query']}")
+        if not args.no_serve:
+            extra["serving"] = serving(scan, torch, ix, g.n, args)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        if scale == 20:
+            log(f"cpu baseline: oracle full build on {threads} threads ...")
+            t = time.perf_counter()
+            oracle.build_index(g, oracle.COSINE, threads=threads)
+            tc = time.perf_counter() - t
+            cpu = {"value": g.num_edges / tc, "unit": "edges/s", "cores": threads, "kind": "oracle",
+                   "sample": f"one full cosine index build of the same R-MAT-20 graph (similarities, neighbour "
+                             f"order, core order), {tc:.1f} s"}
+        else:
+            k = 200_000
+            rng = np.random.default_rng(5)
+            slots = rng.integers(0, g.nnz, k)
+            u = np.searchsorted(g.off, slots, side="right") - 1
+            t = time.perf_counter()
+            oracle.edge_similarities(g, u, g.adj[slots].astype(np.int64), oracle.COSINE)
+            tc = time.perf_counter() - t
+            cpu = {"value": k / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                   "sample": f"similarity of {k} uniformly sampled edges of the same graph, one thread, "
+                             f"{tc:.1f} s (similarity phase only)"}
+        log(f"cpu baseline: {cpu}")
+    extra["cpu_baseline"] = cpu
+    return record(value, args.steps, args.warmup, ms, "f64", config, **extra)
+
+
+def sbm_batch_workload(args, scan, torch, graphgen):
+    t0 = time.time()
+    gs = graphgen.batch_sbm(256)
+    edges = sum(g.num_edges for g in gs)
+    log(f"256 SBM graphs: sum n={sum(g.n for g in gs)} sum |E|={edges} ({time.time() - t0:.1f}s)")
+    dev = [(torch.from_numpy(g.off.astype(np.int64)).cuda(), torch.from_numpy(g.adj).cuda()) for g in gs]
+    torch.cuda.synchronize()
+    tune, tinfo = autotune(scan, dev, scan.COSINE, args.tune, reps=1)
+    ms, dev_ms, profs, _ = timed_builds(
+        scan, torch, lambda: scan.scan_build_index_batch(dev, scan.COSINE, scan.SCAN_PROFILE, tune=tune),
+        args.steps, args.warmup)
+    phases = {k: med(profs, k) for k in PHASES}
+    log(f"merged: {ms:.2f} ms/step, phases {phases}")
+    # 256 separate builds on the same stream, same shapes
+    for off, adj in dev[:4]:
+        scan.scan_build_index(off, adj, scan.COSINE, 0, tune=tune)
+    torch.cuda.synchronize()
+    seq = []
+    for _ in range(max(1, args.steps // 2)):
+        t = time.perf_counter()
+        ixs = [scan.scan_build_index(off, adj, scan.COSINE, 0, tune=tune) for off, adj in dev]
+        torch.cuda.synchronize()
+        seq.append((time.perf_counter() - t) * 1e3)
+        del ixs
+    seq_ms = float(np.median(seq))
+    log(f"sequential: {seq_ms:.2f} ms per 256 builds")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        sample = gs[:32]
+        t = time.perf_counter()
+        for g in sample:
+            oracle.build_index(g, oracle.COSINE, threads=threads)
+        tc = time.perf_counter() - t
+        cpu = {"value": sum(g.num_edges for g in sample) / tc, "unit": "edges/s", "cores": threads,
+               "kind": "oracle", "sample": f"full cosine index builds of the first 32 of the 256 graphs, {tc:.1f} s"}
+        log(f"cpu baseline: {cpu}")
+    config = {"workload": "sbm256_batched_cosine_index_build", "graphs": 256, "seed": 256,
+              "n_range": [1000, 200000], "blocks": [5, 200], "avg_degree": [8, 64], "p_out_over_p_in": 0.02,
+              "sum_n": int(sum(g.n for g in gs)), "edges": int(edges), "offsets": "int64", "tune": tune}
+    return record(edges / (ms * 1e-3), args.steps, args.warmup, ms, "f64", config,
+                  phases_ms=phases, device_ms_per_step=dev_ms, tune=dict(tinfo, **tune),
+                  sequential={"ms_per_256_builds": seq_ms, "edges_per_s": edges / (seq_ms * 1e-3)},
+                  speedup_vs_sequential=seq_ms / ms, cpu_baseline=cpu)
 
 
 def main():
@@ -107,15 +411,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=20)
-    ap.add_argument("--edge-factor", type=int, default=16)
-    ap.add_argument("--seed", type=int, default=20)
+    ap.add_argument("--workload", choices=["rmat20", "rmat23", "sbm256"], default="rmat20")
+    ap.add_argument("--tune", default="auto", help="auto | default | small_max=..,spc=..,wbits=..")
     ap.add_argument("--queries", type=int, default=200)
     ap.add_argument("--query-batch", type=int, default=25)
     ap.add_argument("--serve-queries", type=int, default=20000)
     ap.add_argument("--serve-batch", type=int, default=32)
-    ap.add_argument("--serve-slo-ms", type=float, default=2.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-queries", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -143,145 +446,10 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB read + written")
         del src, dst
-    t0 = time.time()
-    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
-    st = graphgen.degree_stats(g)
-    log(f"graph rmat{args.scale}: n={g.n} |E|={g.num_edges} nnz={g.nnz} dmax={st['dmax']} "
-        f"w_min={st['w_min']} ({time.time() - t0:.1f}s)")
-    off = torch.from_numpy(g.off.astype(np.int32)).cuda()
-    adj = torch.from_numpy(g.adj).cuda()
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-
-    def one_build(profile=False):
-        return scan.scan_build_index(off, adj, scan.COSINE, scan.SCAN_PROFILE if profile else 0)
-
-    for i in range(args.warmup):
-        ix = one_build(True)
-        torch.cuda.synchronize()
-        log(f"warmup {i}: {scan.scan_index_build_profile(ix)}")
-        del ix
-
-    # Timed region: exactly `steps` builds.
-    profiles = []
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    keep = []
-    for _ in range(args.steps):
-        ix = one_build(True)
-        keep.append(ix)
-        if len(keep) > 1:
-            profiles.append(scan.scan_index_build_profile(keep.pop(0)))
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    profiles.append(scan.scan_index_build_profile(keep[-1]))
-    dev_ms = ev0.elapsed_time(ev1)
-    ix = keep[-1]
-    ms_per_step = wall * 1000.0 / args.steps
-    edges = g.num_edges
-    value = edges * args.steps / wall
-    med = lambda key: float(np.median([p[key] for p in profiles]))
-    phases = {k: med(k) for k in ("total_ms", "prepare_ms", "plan_ms", "intersect_ms", "no_sort_ms",
-                                  "core_order_ms")}
-    log(f"build: {ms_per_step:.2f} ms/step wall, device span {dev_ms / args.steps:.2f} ms/step, phases {phases}")
-
-    bm = byte_model(st, 4)
-    int_ms = phases["intersect_ms"]
-    achieved = bm["intersect"] / (int_ms * 1e-3) / 1e9
-    build_gbs = bm["build"] / (phases["total_ms"] * 1e-3) / 1e9
-
-    # Queries: mu ~ U{2..16}, eps ~ U{0.10, 0.15, ..., 0.90}; one at a time
-    # (synchronous) vs batched.
-    rng = np.random.default_rng(7)
-    q_mu = rng.integers(2, 17, args.queries)
-    q_eps = np.array([(10 + 5 * k) / 100.0 for k in rng.integers(0, 17, args.queries)])
-    memb = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    for i in range(5):
-        scan.scan_query(ix, int(q_mu[i]), float(q_eps[i]), memb)
-    torch.cuda.synchronize()
-    single = []
-    for mu, eps in zip(q_mu, q_eps):
-        t = time.perf_counter()
-        scan.scan_query(ix, int(mu), float(eps), memb)
-        torch.cuda.synchronize()
-        single.append((time.perf_counter() - t) * 1e3)
-    B = args.query_batch
-    out = torch.empty((B, g.n), dtype=torch.int32, device="cuda")
-    batched, tb0 = [], time.perf_counter()
-    for i in range(0, args.queries, B):
-        t = time.perf_counter()
-        scan.scan_query_batch(ix, q_mu[i:i + B], q_eps[i:i + B], out[: len(q_mu[i:i + B])])
-        torch.cuda.synchronize()
-        batched += [(time.perf_counter() - t) * 1e3] * len(q_mu[i:i + B])
-    tb = time.perf_counter() - tb0
-    ts = sum(single) / 1e3
-    query = {
-        "mu": "U{2..16}", "eps": "U{0.10,0.15,...,0.90}", "queries": args.queries, "batch": B,
-        "one_at_a_time": {"p50_ms": float(np.percentile(single, 50)), "p99_ms": float(np.percentile(single, 99)),
-                          "qps": args.queries / ts},
-        "batched": {"p50_ms": float(np.percentile(batched, 50)), "p99_ms": float(np.percentile(batched, 99)),
-                    "qps": args.queries / tb},
-    }
-    log(f"queries: {query}")
-
-    serving = None
-    if not args.no_serve:
-        rates = [2500, 5000, 10000, 20000, 40000, 80000, 160000]
-        B = args.serve_batch
-        serving = {"queries_per_rate": args.serve_queries, "arrivals": "poisson", "mu": "U{2..16}",
-                   "eps": "U{0.10,0.15,...,0.90}", "results": "device (HBM)", "p99_slo_ms": args.serve_slo_ms,
-                   "one_at_a_time": serve_ladder(scan, torch, ix, g.n, "one_at_a_time", 1, 1,
-                                                 args.serve_queries, rates, args.serve_slo_ms),
-                   "batched": serve_ladder(scan, torch, ix, g.n, "batched", 4 * B, B,
-                                           args.serve_queries, rates, args.serve_slo_ms)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        log(f"cpu baseline: oracle full build on {threads} threads ...")
-        t = time.perf_counter()
-        oracle.build_index(g, oracle.COSINE, threads=threads)
-        tc = time.perf_counter() - t
-        cpu = {"value": edges / tc, "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": f"one full cosine index build of the same R-MAT-{args.scale} graph "
-                         f"(similarities, neighbour order, core order), {tc:.1f} s"}
-        log(f"cpu baseline: {tc:.1f} s")
-
-    rec = {
-        "metric": "index-build edges/s (R-MAT-20); query p50/p99 ms, batched vs one-at-a-time",
-        "value": value,
-        "unit": "edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}_cosine_index_build", "scale": args.scale,
-                   "edge_factor": args.edge_factor, "abcd": [0.57, 0.19, 0.19, 0.05], "seed": args.seed,
-                   "n": g.n, "edges": edges, "nnz": g.nnz, "dmax": st["dmax"], "w_min": st["w_min"],
-                   "offsets": "int32", "similarity": "cosine", "ids": "int32"},
-        "phases_ms": phases,
-        "device_ms_per_step": dev_ms / args.steps,
-        "query": query,
-        "serving": serving,
-        "roofline": {"bound": "hbm", "kernel": "k_intersect (all degree-class launches of one build)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bm["intersect"], "launch_ms": int_ms},
-        "build_roofline": {"bytes": bm["build"], "floor_bytes": bm["floor"], "achieved": build_gbs,
-                           "frac": build_gbs / HBM_PEAK_GBS,
-                           "floor_frac": bm["floor"] / (phases["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "cpu_baseline": cpu,
-    }
+    if args.workload == "sbm256":
+        rec = sbm_batch_workload(args, scan, torch, graphgen)
+    else:
+        rec = rmat_workload(args, scan, torch, graphgen)
     print(json.dumps(rec), flush=True)
 
 

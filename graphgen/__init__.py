@@ -66,6 +66,8 @@ def _load():
     lib.gg_unit.restype = ctypes.c_double
     lib.gg_degree_stats.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p] + [P(ctypes.c_int64)] * 4
     lib.gg_degree_stats.restype = None
+    lib.gg_owner_split.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.gg_owner_split.restype = None
     _lib = lib
     return lib
 
@@ -157,6 +159,17 @@ def degree_stats(g: Graph) -> dict:
     dmax, noniso, wmin, s2 = (int(v.value) for v in vals)
     return {"n": g.n, "nnz": g.nnz, "edges": g.nnz // 2, "dmax": dmax, "non_isolated": noniso,
             "w_min": wmin, "sum_deg2": s2}
+
+
+def owner_split(g: Graph, small_max: int) -> dict:
+    """Edges and W_min split by owner class: an edge is owned by its endpoint
+    larger in (degree, id), and owners of degree <= small_max are "small"."""
+    off = np.ascontiguousarray(g.off, dtype=np.int64)
+    adj = np.ascontiguousarray(g.adj, dtype=np.int32)
+    out = np.zeros(4, np.int64)
+    _load().gg_owner_split(g.n, off.ctypes.data, adj.ctypes.data if len(adj) else None, int(small_max),
+                           out.ctypes.data)
+    return {"edges_small": int(out[0]), "w_small": int(out[1]), "edges_big": int(out[2]), "w_big": int(out[3])}
 
 
 # ---------------------------------------------------------------------------

@@ -225,4 +225,35 @@ void gg_degree_stats(int64_t n, const int64_t *off, const int32_t *adj, int64_t 
   *sum_deg2 = s2;
 }
 
+// Work split by edge owner: an edge belongs to its endpoint that is larger in
+// (degree, id); owners of degree <= small_max form the "small" class. out[0..3]
+// = edges and summed min-degree of small-owned edges, then of the others.
+void gg_owner_split(int64_t n, const int64_t *off, const int32_t *adj, int64_t small_max,
+                    int64_t *out) {
+  int64_t es = 0, ws = 0, eb = 0, wb = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : es, ws, eb, wb)
+  for (int64_t u = 0; u < n; ++u) {
+    const int64_t du = off[u + 1] - off[u];
+    for (int64_t s = off[u]; s < off[u + 1]; ++s) {
+      const int64_t v = adj[s];
+      if (v <= u) continue;
+      const int64_t dv = off[v + 1] - off[v];
+      const bool u_owns = du > dv || (du == dv && u > v);
+      const int64_t downer = u_owns ? du : dv;
+      const int64_t w = std::min(du, dv);
+      if (downer <= small_max) {
+        ++es;
+        ws += w;
+      } else {
+        ++eb;
+        wb += w;
+      }
+    }
+  }
+  out[0] = es;
+  out[1] = ws;
+  out[2] = eb;
+  out[3] = wb;
+}
+
 }  // extern "C"

@@ -67,7 +67,9 @@ enum {
  * from hipEvents recorded on the build stream between phases:
  *   prepare     degrees, offsets, max degree (and validation if asked)
  *   plan        edge ownership and chunk lists per table class
- *   intersect   all intersection + similarity launches
+ *   intersect   all intersection + similarity launches, split into
+ *               intersect_small (owners of degree <= small_max, one
+ *               wavefront each) and intersect_big (bitmap-window owners)
  *   no_sort     neighbour-order segmented sort
  *   core_order  core-order sizes, placement and segmented sort
  * total spans all of them (host synchronisation gaps included). */
@@ -78,8 +80,12 @@ typedef struct {
   double intersect_ms;
   double no_sort_ms;
   double core_order_ms;
+  double intersect_small_ms;
+  double intersect_big_ms;
   int32_t intersect_launches;
-  int32_t owners;       /* vertices that own at least one edge */
+  int32_t small_owners;  /* vertices of degree 1..small_max (LDS hash path) */
+  int32_t big_chunks;    /* row chunks of larger vertices (bitmap path)    */
+  int32_t window_bits;   /* bitmap window used (2^window_bits ids)         */
 } scan_build_profile;
 
 /* A graph in CSR form. offsets has n+1 entries of offset_bits (32 or 64)
@@ -258,7 +264,9 @@ typedef struct scan_server scan_server;
 scan_status scan_server_create(const scan_index *ix, const scan_server_opts *opts,
                                scan_server **out);
 /* Queues (mu, eps); the memberships (int32[n], as scan_query's) are written
- * to host `dst`, which must stay valid until the ticket completes.
+ * to host `dst`, which must stay valid until the ticket completes. Pinned
+ * host memory (hipHostMalloc) is written by the device directly; pageable
+ * memory goes through the server's pinned staging and one host copy.
  * SCAN_EBUSY when the request queue (4 * slots, at least 64) is full: nothing
  * is queued and the caller retries later. SCAN_EINVAL for mu < 2 or NaN eps.
  * *ticket (> 0) identifies the request. */
@@ -289,6 +297,15 @@ void scan_server_destroy(scan_server *s);
  * SCAN_ENOMEM, SCAN_EDEVICE. */
 scan_status scan_similarity_values(scan_sim_kind kind, int64_t count, const int64_t *c,
                                    const int64_t *a_u, const int64_t *a_v, double *out);
+
+/* Diagnostic: the segmented sort the neighbour and core orders use, on HOST
+ * arrays. Segment i is [seg_off[i], seg_off[i+1]) (seg_off[0] = 0, non-
+ * decreasing); each is sorted by key descending, ties by id ascending (the
+ * order of Algorithm 2's rows and segments), into keys_out / ids_out.
+ * Keys must be positive finite doubles, ids in [0, INT32_MAX). Synchronous,
+ * on the default stream. Errors: SCAN_EINVAL, SCAN_ENOMEM, SCAN_EDEVICE. */
+scan_status scan_segmented_sort(const int64_t *seg_off, int64_t nseg, const double *keys,
+                                const int32_t *ids, double *keys_out, int32_t *ids_out);
 
 /* Thread-local message describing the last failure on this thread. */
 const char *scan_last_error(void);

@@ -55,6 +55,8 @@ def _load():
     lib.oracle_edge_similarity.restype = f64
     lib.oracle_neighbor_order.argtypes = [i64, vp, vp, vp, i32, vp, vp]
     lib.oracle_neighbor_order.restype = None
+    lib.oracle_neighbor_order_row.argtypes = [i64, vp, vp, vp, vp]
+    lib.oracle_neighbor_order_row.restype = None
     lib.oracle_core_order.argtypes = [i64, vp, vp, i64, i32, vp, vp, vp]
     lib.oracle_core_order.restype = None
     lib.oracle_query.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, i32, f64, vp, vp]
@@ -135,6 +137,16 @@ def neighbor_order(g, sim: np.ndarray, threads: int = 1):
     _load().oracle_neighbor_order(g.n, _p(off), _p(adj), _p(np.ascontiguousarray(sim)), threads,
                                   _p(no_ids), _p(no_sim))
     return no_ids, no_sim
+
+
+def neighbor_order_row(ids: np.ndarray, sim: np.ndarray):
+    """One row of the neighbour order: (ids, sims) sorted by sim desc, id asc."""
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    sim = np.ascontiguousarray(sim, dtype=np.float64)
+    out_i = np.zeros(len(ids), np.int32)
+    out_s = np.zeros(len(ids), np.float64)
+    _load().oracle_neighbor_order_row(len(ids), _p(ids), _p(sim), _p(out_i), _p(out_s))
+    return out_i, out_s
 
 
 def core_order(g, no_sim: np.ndarray, dmax: int, threads: int = 1):

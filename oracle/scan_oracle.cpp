@@ -175,16 +175,23 @@ double oracle_edge_similarity(const int64_t *off, const int32_t *adj, int32_t ki
 
 // Algorithm 2, MakeNeighborOrder: each row sorted by non-increasing
 // similarity, ties by lower id.
+// One row: ids[0..d) with their similarities sim[0..d) -> sorted copy.
+void oracle_neighbor_order_row(int64_t d, const int32_t *ids, const double *sim, int32_t *no_ids,
+                               double *no_sim) {
+  std::vector<Entry> row;
+  for (int64_t i = 0; i < d; ++i) row.push_back({sim[i], ids[i]});
+  std::stable_sort(row.begin(), row.end(), before);
+  for (size_t i = 0; i < row.size(); ++i) {
+    no_ids[i] = row[i].id;
+    no_sim[i] = row[i].key;
+  }
+}
+
 void oracle_neighbor_order(int64_t n, const int64_t *off, const int32_t *adj, const double *sim,
                            int32_t threads, int32_t *no_ids, double *no_sim) {
   parallel_for_dynamic(n, threads, [&](int64_t v) {
-    std::vector<Entry> row;
-    for (int64_t s = off[v]; s < off[v + 1]; ++s) row.push_back({sim[s], adj[s]});
-    std::stable_sort(row.begin(), row.end(), before);
-    for (size_t i = 0; i < row.size(); ++i) {
-      no_ids[off[v] + i] = row[i].id;
-      no_sim[off[v] + i] = row[i].key;
-    }
+    oracle_neighbor_order_row(off[v + 1] - off[v], adj + off[v], sim + off[v], no_ids + off[v],
+                              no_sim + off[v]);
   });
 }
 

@@ -54,8 +54,9 @@ class _Info(ctypes.Structure):
 class _Profile(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("prepare_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
                 ("intersect_ms", ctypes.c_double), ("no_sort_ms", ctypes.c_double),
-                ("core_order_ms", ctypes.c_double), ("intersect_launches", ctypes.c_int32),
-                ("owners", ctypes.c_int32)]
+                ("core_order_ms", ctypes.c_double), ("intersect_small_ms", ctypes.c_double),
+                ("intersect_big_ms", ctypes.c_double), ("intersect_launches", ctypes.c_int32),
+                ("small_owners", ctypes.c_int32), ("big_chunks", ctypes.c_int32), ("window_bits", ctypes.c_int32)]
 
 
 class _Tune(ctypes.Structure):
@@ -78,7 +79,7 @@ EXPORTS = [
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
     "scan_version", "scan_similarity_values", "scan_index_build_profile", "scan_build_index_ex",
-    "scan_autotune",
+    "scan_autotune", "scan_segmented_sort",
 ]
 
 _lib = None
@@ -91,6 +92,14 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2012_11188_amd.build_lib`")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one. Loading torch first makes the library bind to that copy, so the
+    # process has one HIP runtime; loading the library first would bring in a
+    # second one, and the two do not share devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64, f64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_uint32, ctypes.c_uint64)
@@ -101,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "scan_build_index_batch": ([P(_Csr), i32, i32, u32, vp, P(vp)], i32),
         "scan_build_index_ex": ([P(_Csr), i32, i32, u32, P(_Tune), vp, P(vp)], i32),
         "scan_autotune": ([P(_Csr), i32, i32, i32, vp, P(_Tune), P(ctypes.c_float)], i32),
+        "scan_segmented_sort": ([vp, i64, vp, vp, vp, vp], i32),
         "scan_query": ([vp, i32, f64, vp], i32),
         "scan_query_ex": ([vp, i32, f64, vp, vp, i32, vp], i32),
         "scan_query_batch": ([vp, i32, vp, vp, vp, i32, vp], i32),
@@ -302,6 +312,19 @@ def scan_build_index_batch(graphs, kind: int = COSINE, flags: int = 0, stream=No
                                        outs))
     del keep
     return [Index(outs[i], s) for i in range(len(arr))]
+
+
+def scan_segmented_sort(seg_off: np.ndarray, keys: np.ndarray, ids: np.ndarray):
+    """Diagnostic: per segment, (keys, ids) sorted by key desc, id asc."""
+    lib = _ready()
+    seg_off = np.ascontiguousarray(seg_off, dtype=np.int64)
+    keys = np.ascontiguousarray(keys, dtype=np.float64)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    ko = np.empty_like(keys)
+    io = np.empty_like(ids)
+    _check(lib.scan_segmented_sort(seg_off.ctypes.data, len(seg_off) - 1, keys.ctypes.data, ids.ctypes.data,
+                                   ko.ctypes.data, io.ctypes.data))
+    return ko, io
 
 
 def scan_autotune(graphs, kind: int = COSINE, reps: int = 2, stream=None) -> dict:

@@ -260,7 +260,7 @@ scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind,
       c.*field = v;
       float ms;
       SCAN_TRY(time_cfg(c, &ms));
-      if (ms < cur_ms) {
+      if (ms < 0.98f * cur_ms) {  // a clear gain only: keeps the choice stable under noise
         cur = c;
         cur_ms = ms;
       }
@@ -337,16 +337,23 @@ scan_status scan_index_build_profile(const scan_index *ix, scan_build_profile *o
   SCAN_HIP_TRY(hipEventSynchronize(ev[5]));
   float t[6] = {0, 0, 0, 0, 0, 0};
   for (int k = 1; k < 6; ++k) SCAN_HIP_TRY(hipEventElapsedTime(&t[k], ev[k - 1], ev[k]));
-  float total = 0;
+  float total = 0, small = 0, big = 0;
   SCAN_HIP_TRY(hipEventElapsedTime(&total, ev[0], ev[5]));
+  SCAN_HIP_TRY(hipEventElapsedTime(&small, ev[2], ev[6]));
+  SCAN_HIP_TRY(hipEventElapsedTime(&big, ev[6], ev[3]));
   out->total_ms = total;
   out->prepare_ms = t[1];
   out->plan_ms = t[2];
   out->intersect_ms = t[3];
   out->no_sort_ms = t[4];
   out->core_order_ms = t[5];
+  out->intersect_small_ms = small;
+  out->intersect_big_ms = big;
+  const int32_t *pc = ix->prof->plan_counts;  // (light, chunks, -, heavy), complete at ev[5]
+  out->small_owners = pc[0] + pc[3];
+  out->big_chunks = pc[1];
   out->intersect_launches = ix->prof->intersect_launches;
-  out->owners = ix->prof->owners;
+  out->window_bits = ix->prof->window_bits;
   return SCAN_OK;
 }
 
@@ -377,6 +384,22 @@ scan_status scan_similarity_values(scan_sim_kind kind, int64_t count, const int6
   if (count == 0) return SCAN_OK;
   if (!c || !a_u || !a_v || !out) return fail(SCAN_EINVAL, "null argument");
   return similarity_values((int32_t)kind, count, c, a_u, a_v, out);
+}
+
+scan_status scan_segmented_sort(const int64_t *seg_off, int64_t nseg, const double *keys,
+                                const int32_t *ids, double *keys_out, int32_t *ids_out) {
+  if (nseg < 0 || (nseg > 0 && !seg_off)) return fail(SCAN_EINVAL, "bad segment offsets");
+  if (nseg == 0) return SCAN_OK;
+  if (seg_off[0] != 0) return fail(SCAN_EINVAL, "seg_off[0] must be 0");
+  for (int64_t i = 0; i < nseg; ++i)
+    if (seg_off[i + 1] < seg_off[i]) return fail(SCAN_EINVAL, "segment offsets decrease at %lld", (long long)i);
+  const int64_t total = seg_off[nseg];
+  if (total > 0 && (!keys || !ids || !keys_out || !ids_out)) return fail(SCAN_EINVAL, "null argument");
+  for (int64_t i = 0; i < total; ++i) {
+    if (!(keys[i] > 0.0) || std::isinf(keys[i])) return fail(SCAN_EINVAL, "keys must be positive and finite");
+    if (ids[i] < 0 || ids[i] == INT32_MAX) return fail(SCAN_EINVAL, "ids must be in [0, INT32_MAX)");
+  }
+  return segmented_sort_values(seg_off, nseg, keys, ids, keys_out, ids_out);
 }
 
 const char *scan_version(void) { return "scan-mi355x 0.1 (gfx950)"; }

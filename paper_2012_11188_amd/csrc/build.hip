@@ -34,6 +34,7 @@ BuildProfileEvents::~BuildProfileEvents() {
       (void)hipEventSynchronize(e);
       (void)hipEventDestroy(e);
     }
+  if (plan_counts) (void)hipHostFree(plan_counts);
 }
 
 // Per-graph description of a batch member (device copy).
@@ -61,7 +62,9 @@ __device__ __forceinline__ int find_graph(const int64_t *base, int G, int64_t x)
 // a1: union CSR, degrees, per-graph maximum degree. Work items of graph g:
 // its n+1 offsets, then (when the adjacency is copied) its nnz ids.
 
-__global__ void k_union_prepare(const GraphDesc *gd, const int64_t *item_base, int G,
+constexpr int kPrepThreads = 256;
+
+__global__ __launch_bounds__(kPrepThreads) void k_union_prepare(const GraphDesc *gd, const int64_t *item_base, int G,
                                 int64_t total, int copy_adj, int64_t *off_u, int32_t *deg_u,
                                 int32_t *adj_u, unsigned *dmax_g) {
   // running maximum degree of the graph this thread last visited, flushed
@@ -98,14 +101,35 @@ __global__ void k_union_prepare(const GraphDesc *gd, const int64_t *item_base, i
       adj_u[d.ebase + s] = (int32_t)(d.vbase + d.adj[s]);
     }
   }
+  // Wavefronts whose lanes all saw one graph reduce in registers; the block
+  // then issues one atomic per run of waves with the same graph (usually one
+  // per block). Other lanes flush on their own (blocks at graph boundaries).
+  __shared__ int32_t wg[kPrepThreads / kWave];
+  __shared__ unsigned wm[kPrepThreads / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int g0 = __builtin_amdgcn_readfirstlane(gl);
-  if (__all(gl == g0)) {
-    unsigned m = ml;
+  const bool uni = __all(gl == g0);
+  unsigned m = ml;
 #pragma unroll
-    for (int k = kWave / 2; k > 0; k >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, k, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && g0 >= 0) atomicMax(&dmax_g[g0], m);
-  } else if (gl >= 0) {
-    atomicMax(&dmax_g[gl], ml);
+  for (int k = kWave / 2; k > 0; k >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, k, kWave));
+  if (lane == 0) {
+    wg[wave] = uni ? g0 : -1;
+    wm[wave] = m;
+  }
+  if (!uni && gl >= 0) atomicMax(&dmax_g[gl], ml);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cg = -1;
+    unsigned cm = 0;
+    for (int w = 0; w < kPrepThreads / kWave; ++w) {
+      if (wg[w] != cg) {
+        if (cg >= 0) atomicMax(&dmax_g[cg], cm);
+        cg = wg[w];
+        cm = 0;
+      }
+      cm = max(cm, wm[w]);
+    }
+    if (cg >= 0) atomicMax(&dmax_g[cg], cm);
   }
 }
 
@@ -208,6 +232,45 @@ __global__ __launch_bounds__(256) void k_graph_hist(const VTile *tiles, int64_t 
   }
 }
 
+// Core-order sizes from the degree histograms (P = exclusive scan of all
+// graphs' histograms, so graph g's prefix is P[hbase[g] + d] - P[hbase[g]]):
+//   E[d] = number of vertices of degree < d           (d = 0..dmax+1)
+//   X[mu - 2] = |CO[mu]| = n - E[mu - 1]              (mu = 2..dmax+1)
+// Flat over all graphs' entries.
+__global__ void k_co_counts(const int64_t *P, const int64_t *hbase, const int64_t *Ebase,
+                            const int64_t *segbase, const int64_t *n_g, int G, int64_t *E_all,
+                            int64_t *X) {
+  const int64_t total = Ebase[G];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = find_graph(Ebase, G, i);
+    const int64_t d = i - Ebase[g], dm = Ebase[g + 1] - Ebase[g] - 2;
+    const int64_t e = P[hbase[g] + d] - P[hbase[g]];
+    E_all[i] = e;
+    if (d >= 1 && d <= dm) X[segbase[g] + d - 1] = n_g[g] - e;
+  }
+}
+
+// Core-order offsets co[mu] = sum of |CO[m]| for 2 <= m < mu (XS = exclusive
+// scan of X over all graphs), the union start of each segment for the sort
+// (the end of the last one is the total), and the non-isolated counts.
+__global__ void k_co_offsets(const int64_t *XS, const int64_t *cobase, const int64_t *segbase,
+                             const int64_t *ebase, const int64_t *hbase, const int32_t *hist_all,
+                             const int64_t *n_g, int G, int64_t *co_all, int64_t *seg_all,
+                             int64_t *nz_g) {
+  const int64_t total = cobase[G];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = find_graph(cobase, G, i);
+    const int64_t mu = i - cobase[g], dm = cobase[g + 1] - cobase[g] - 3;
+    const int64_t co = mu < 2 ? 0 : XS[segbase[g] + mu - 2] - XS[segbase[g]];
+    co_all[i] = co;
+    if (mu >= 2 && mu <= dm + 1) seg_all[segbase[g] + mu - 2] = ebase[g] + co;
+    if (mu == 0) nz_g[g] = dm > 0 ? n_g[g] - hist_all[hbase[g]] : 0;
+    if (i == 0) seg_all[segbase[G]] = ebase[G];
+  }
+}
+
 // Rank of every non-isolated vertex of its graph, degree-descending (ties in
 // any order: each CO segment is sorted afterwards): r = #{deg > d} + the
 // vertex's position among those of degree d, from LDS counters per tile plus
@@ -254,11 +317,16 @@ __global__ __launch_bounds__(256) void k_co_rank(const VTile *tiles, int64_t nti
 }
 
 // Number of mu tiles of each rank tile (its first rank has the top degree).
+// Rank tiles are planned from n (known on the host); those past the graph's
+// non-isolated count get no mu tiles.
 __global__ void k_co_tiles(const RTile *rt, int64_t nrt, const int32_t *sv_all,
-                           const int64_t *svbase, const int32_t *deg, int32_t *tiles_of) {
+                           const int64_t *svbase, const int64_t *nz_g, const int32_t *deg,
+                           int32_t *tiles_of) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nrt;
        t += (int64_t)gridDim.x * blockDim.x)
-    tiles_of[t] = (deg[sv_all[svbase[rt[t].g] + rt[t].r0]] + kFillMu - 1) / kFillMu;
+    tiles_of[t] = rt[t].r0 < nz_g[rt[t].g]
+                      ? (deg[sv_all[svbase[rt[t].g] + rt[t].r0]] + kFillMu - 1) / kFillMu
+                      : 0;
 }
 
 // One workgroup per (rank tile, mu tile): kFillRanks consecutive ranks x
@@ -268,8 +336,9 @@ __global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
                                                  const int64_t *tile_first, const int32_t *sv_all,
                                                  const int64_t *svbase, const int64_t *nz_g,
                                                  const int32_t *deg, const int64_t *off,
-                                                 const double *no_sim, const int64_t *coabs_all,
-                                                 const int64_t *coabs_base, const int64_t *vbase,
+                                                 const double *no_sim, const int64_t *co_all,
+                                                 const int64_t *cobase, const int64_t *ebase,
+                                                 const int64_t *vbase,
                                                  double *co_key, int32_t *co_id) {
   __shared__ double tile[kFillMu][kFillRanks + 1];
   __shared__ int32_t vs[kFillRanks], vd[kFillRanks];
@@ -292,7 +361,8 @@ __global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
     const RTile r = rt[s_t];
     const int64_t r0 = r.r0;
     const int32_t j0 = (int32_t)(s_k * kFillMu);
-    const int64_t *coabs = coabs_all + coabs_base[r.g];
+    const int64_t *co = co_all + cobase[r.g];  // relative offsets of graph r.g
+    const int64_t eb = ebase[r.g];
     const int32_t vb = (int32_t)vbase[r.g];
     if (threadIdx.x < kFillRanks) {
       const int64_t rr = r0 + threadIdx.x;
@@ -316,7 +386,7 @@ __global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
     for (int e = threadIdx.x; e < kFillRanks * kFillMu; e += blockDim.x) {
       const int j = e / kFillRanks, i = e % kFillRanks;
       if (j0 + j < vd[i]) {
-        const int64_t pos = coabs[j0 + j + 2] + r0 + i;
+        const int64_t pos = eb + co[j0 + j + 2] + r0 + i;
         co_key[pos] = tile[j][i];
         co_id[pos] = vs[i];
       }
@@ -395,6 +465,32 @@ scan_status to_device(DevArena &tmp, T **dst, const std::vector<T> &src, hipStre
   return SCAN_OK;
 }
 
+// Host tables gathered into one buffer (each entry 16-byte aligned) and sent
+// to the device with one copy.
+class HostPack {
+ public:
+  template <class T>
+  size_t add(const std::vector<T> &v) {
+    const size_t at = (buf_.size() + 15) & ~(size_t)15;
+    buf_.resize(at + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(buf_.data() + at, v.data(), v.size() * sizeof(T));
+    return at;
+  }
+  scan_status upload(DevArena &tmp, hipStream_t s, unsigned char **dev) {
+    SCAN_TRY(tmp.alloc(dev, (int64_t)std::max<size_t>(buf_.size(), 16)));
+    if (!buf_.empty())
+      SCAN_HIP_TRY(hipMemcpyAsync(*dev, buf_.data(), buf_.size(), hipMemcpyHostToDevice, s));
+    return SCAN_OK;
+  }
+  template <class T>
+  static const T *at(const unsigned char *dev, size_t off) {
+    return (const T *)(dev + off);
+  }
+
+ private:
+  std::vector<unsigned char> buf_;
+};
+
 }  // namespace
 
 scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint32_t flags,
@@ -428,6 +524,8 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   if (flags & SCAN_PROFILE) {
     prof = std::make_shared<BuildProfileEvents>();
     for (auto &e : prof->ev) SCAN_HIP_TRY(hipEventCreate(&e));
+    SCAN_HIP_TRY(hipHostMalloc((void **)&prof->plan_counts, 4 * sizeof(int32_t), hipHostMallocDefault));
+    for (int k = 0; k < 4; ++k) prof->plan_counts[k] = 0;
   }
   auto mark = [&](int k) {
     if (prof) (void)hipEventRecord(prof->ev[k], s);
@@ -490,7 +588,7 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       SCAN_HIP_TRY(hipStreamSynchronize(s));
     }
     if (total > 0)
-      k_union_prepare<<<grid_for(total, 256), 256, 0, s>>>(d_gd, d_item_base, G, total, copy_adj ? 1 : 0,
+      k_union_prepare<<<grid_for(total, kPrepThreads, 1024), kPrepThreads, 0, s>>>(d_gd, d_item_base, G, total, copy_adj ? 1 : 0,
                                                           off_u, deg, adj_u, d_dmax);
   }
   if (flags & SCAN_VALIDATE) {
@@ -516,12 +614,8 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       if (herr[2 * g])
         return fail(SCAN_EGRAPH, "graph %d is not a simple undirected CSR with ascending rows (first bad row %d)", g, herr[2 * g + 1]);
   }
-  std::vector<unsigned> hdmax(G);
-  SCAN_HIP_TRY(hipMemcpyAsync(hdmax.data(), d_dmax, (size_t)G * 4, hipMemcpyDeviceToHost, s));
-  SCAN_HIP_TRY(hipStreamSynchronize(s));
-  SCAN_HIP_TRY(hipGetLastError());
-  mark(1);
-
+  // Index arrays (their sizes do not depend on the degrees): allocated while
+  // the device runs the kernels above.
   int32_t *no_ids, *co_ids, *counts = nullptr;
   double *no_sim, *co_thr, *sims;
   SCAN_TRY(arena_alloc(*arena, &no_ids, NNZ));
@@ -532,127 +626,132 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   else SCAN_TRY(tmp.alloc(&sims, NNZ));
   if (flags & SCAN_KEEP_COUNTS) SCAN_TRY(arena_alloc(*arena, &counts, NNZ));
 
-  // Per-graph core-order bookkeeping (host), filled below.
-  std::vector<int64_t> hbase(G + 1, 0), Ebase(G + 1, 0), cobase(G + 1, 0), ng(G), nz(G, 0), svbase(G + 1, 0);
+  std::vector<unsigned> hdmax(G);
+  SCAN_HIP_TRY(hipMemcpyAsync(hdmax.data(), d_dmax, (size_t)G * 4, hipMemcpyDeviceToHost, s));
+  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  SCAN_HIP_TRY(hipGetLastError());
+  mark(1);
+
+  // Host tables for the rest of the build; everything they hold is known once
+  // the maximum degrees are. They go to the device in one copy, now, while
+  // the device is idle; the core-order sizes themselves are computed there.
+  std::vector<int64_t> hbase(G + 1, 0), Ebase(G + 1, 0), cobase(G + 1, 0), segbase(G + 1, 0), ng(G),
+      obase(G + 1, 0);
   for (int32_t g = 0; g < G; ++g) {
     hbase[g + 1] = hbase[g] + hdmax[g] + 1;
     Ebase[g + 1] = Ebase[g] + hdmax[g] + 2;
     cobase[g + 1] = cobase[g] + hdmax[g] + 3;
+    segbase[g + 1] = segbase[g] + hdmax[g];  // segments mu = 2..dmax+1
+    obase[g + 1] = obase[g] + gs[g].n + 1;
     ng[g] = gs[g].n;
   }
-  std::vector<int64_t> corel(cobase[G], 0);  // per-graph co_off, relative
+  std::vector<VTile> vt;
+  std::vector<RTile> rt;
+  for (int32_t g = 0; g < G; ++g) {
+    for (int64_t v0 = vbase[g]; v0 < vbase[g + 1]; v0 += kRankTile)
+      vt.push_back(VTile{g, 0, v0, std::min(vbase[g + 1], v0 + kRankTile)});
+    for (int64_t r0 = 0; r0 < gs[g].n; r0 += kFillRanks) rt.push_back(RTile{g, (int32_t)r0});
+  }
+  HostPack pack;
+  const size_t p_hbase = pack.add(hbase), p_Ebase = pack.add(Ebase), p_cobase = pack.add(cobase),
+               p_segbase = pack.add(segbase), p_ng = pack.add(ng), p_obase = pack.add(obase),
+               p_vbase = pack.add(vbase), p_ebase = pack.add(ebase), p_vt = pack.add(vt), p_rt = pack.add(rt);
+  unsigned char *dpack;
+  SCAN_TRY(pack.upload(tmp, s, &dpack));
+  const int64_t *d_hbase = pack.at<int64_t>(dpack, p_hbase), *d_Ebase = pack.at<int64_t>(dpack, p_Ebase),
+                *d_cobase = pack.at<int64_t>(dpack, p_cobase), *d_segbase = pack.at<int64_t>(dpack, p_segbase),
+                *d_ng = pack.at<int64_t>(dpack, p_ng), *d_obase = pack.at<int64_t>(dpack, p_obase),
+                *d_vbase = pack.at<int64_t>(dpack, p_vbase), *d_ebase = pack.at<int64_t>(dpack, p_ebase);
+  const VTile *d_vt = pack.at<VTile>(dpack, p_vt);
+  const RTile *d_rt = pack.at<RTile>(dpack, p_rt);
+  int64_t *d_corel;  // per-graph core-order offsets (the indexes' co_off)
+  SCAN_TRY(arena_alloc(*arena, &d_corel, cobase[G]));
 
   if (NNZ > 0) {
     // a2-a4: ownership plan, intersection and similarity over the union.
     IntersectStats ist;
     if (prof) {
       ist.ev_start = prof->ev[2];
+      ist.ev_mid = prof->ev[6];
       ist.ev_end = prof->ev[3];
+      ist.host_counts = prof->plan_counts;
     }
     SCAN_TRY(intersect_all(cfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
     if (prof) {
-      prof->owners = ist.owners_small;
-      prof->intersect_launches = (ist.owners_small > 0) + (ist.chunks_big > 0);
+      prof->window_bits = ist.wbits;
+      prof->intersect_launches = ist.launches;
     }
 
     // a5: neighbour order, then ids made local to each graph.
     SCAN_TRY(segmented_sort(off_u, N, NNZ, sims, adj_u, no_sim, no_ids, s));
-    int64_t *d_vbase, *d_ebase;
-    SCAN_TRY(to_device(tmp, &d_vbase, vbase, s));
-    SCAN_TRY(to_device(tmp, &d_ebase, ebase, s));
     if (G > 1) k_localize_ids<<<grid_for(NNZ, 256), 256, 0, s>>>(no_ids, d_ebase, d_vbase, G, NNZ);
     mark(4);
 
-    // a6: core order. Degree histograms per graph -> sizes (host).
-    std::vector<VTile> vt;
-    for (int32_t g = 0; g < G; ++g)
-      for (int64_t v0 = vbase[g]; v0 < vbase[g + 1]; v0 += kRankTile)
-        vt.push_back(VTile{g, 0, v0, std::min(vbase[g + 1], v0 + kRankTile)});
-    VTile *d_vt;
-    int64_t *d_hbase;
-    int32_t *d_hist, *d_cursor;
-    SCAN_TRY(to_device(tmp, &d_vt, vt, s));
-    SCAN_TRY(to_device(tmp, &d_hbase, hbase, s));
-    SCAN_TRY(tmp.alloc(&d_hist, hbase[G]));
-    SCAN_TRY(tmp.alloc(&d_cursor, hbase[G]));
-    SCAN_HIP_TRY(hipMemsetAsync(d_hist, 0, (size_t)hbase[G] * 4, s));
-    SCAN_HIP_TRY(hipMemsetAsync(d_cursor, 0, (size_t)hbase[G] * 4, s));
-    if (!vt.empty())
-      k_graph_hist<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, s>>>(d_vt, (int64_t)vt.size(), deg, d_hbase, d_dmax, d_hist);
-    std::vector<int32_t> hist(hbase[G]);
-    SCAN_HIP_TRY(hipMemcpyAsync(hist.data(), d_hist, hist.size() * 4, hipMemcpyDeviceToHost, s));
-    SCAN_HIP_TRY(hipStreamSynchronize(s));
-    std::vector<int64_t> E(Ebase[G]), coabs(cobase[G]), seg;
-    std::vector<RTile> rt;
-    seg.reserve(hbase[G] + 1);
-    for (int32_t g = 0; g < G; ++g) {
-      const int64_t dm = hdmax[g], n = gs[g].n;
-      int64_t *Eg = &E[Ebase[g]];
-      int64_t *cr = &corel[cobase[g]];
-      Eg[0] = 0;
-      for (int64_t d = 0; d <= dm; ++d) Eg[d + 1] = Eg[d] + hist[hbase[g] + d];
-      cr[0] = cr[1] = cr[2] = 0;
-      for (int64_t mu = 2; mu <= dm + 1; ++mu) cr[mu + 1] = cr[mu] + (n - Eg[mu - 1]);
-      for (int64_t mu = 0; mu <= dm + 2; ++mu) coabs[cobase[g] + mu] = ebase[g] + cr[mu];
-      for (int64_t mu = 2; mu <= dm + 1; ++mu) seg.push_back(ebase[g] + cr[mu]);
-      nz[g] = dm > 0 ? n - hist[hbase[g]] : 0;
-      svbase[g + 1] = svbase[g] + nz[g];
-      for (int64_t r0 = 0; r0 < nz[g]; r0 += kFillRanks) rt.push_back(RTile{g, (int32_t)r0});
-    }
-    seg.push_back(NNZ);
-    int64_t *d_E, *d_Ebase, *d_coabs, *d_cobase, *d_seg, *d_ng, *d_nz, *d_svbase, *d_tile_first, *scan_ws;
-    RTile *d_rt;
-    int32_t *d_sv, *d_tiles_of;
+    // a6: core order: degree histograms, sizes and offsets (device), ranks,
+    // transposed fill, segmented sort.
+    int32_t *d_hist, *d_cursor, *d_sv, *d_tiles_of;
+    int64_t *d_E, *d_seg, *d_nz, *d_tile_first, *scan_ws;
     double *co_key;
     int32_t *co_id;
-    SCAN_TRY(to_device(tmp, &d_E, E, s));
-    SCAN_TRY(to_device(tmp, &d_Ebase, Ebase, s));
-    SCAN_TRY(to_device(tmp, &d_coabs, coabs, s));
-    SCAN_TRY(to_device(tmp, &d_cobase, cobase, s));
-    SCAN_TRY(to_device(tmp, &d_seg, seg, s));
-    SCAN_TRY(to_device(tmp, &d_ng, ng, s));
-    SCAN_TRY(to_device(tmp, &d_nz, nz, s));
-    SCAN_TRY(to_device(tmp, &d_svbase, svbase, s));
-    SCAN_TRY(to_device(tmp, &d_rt, rt, s));
     const int64_t nrt = (int64_t)rt.size();
-    SCAN_TRY(tmp.alloc(&d_sv, std::max<int64_t>(svbase[G], 1)));
+    SCAN_TRY(tmp.alloc(&d_hist, hbase[G]));
+    SCAN_TRY(tmp.alloc(&d_cursor, hbase[G]));
+    SCAN_TRY(tmp.alloc(&d_E, Ebase[G]));
+    SCAN_TRY(tmp.alloc(&d_seg, segbase[G] + 1));
+    SCAN_TRY(tmp.alloc(&d_nz, G));
+    SCAN_TRY(tmp.alloc(&d_sv, std::max<int64_t>(N, 1)));
     SCAN_TRY(tmp.alloc(&d_tiles_of, std::max<int64_t>(nrt, 1)));
     SCAN_TRY(tmp.alloc(&d_tile_first, nrt + 1));
     SCAN_TRY(tmp.alloc(&scan_ws, scan_workspace_elems(std::max<int64_t>(nrt, 1))));
     SCAN_TRY(tmp.alloc(&co_key, NNZ));
     SCAN_TRY(tmp.alloc(&co_id, NNZ));
-    k_co_rank<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, s>>>(d_vt, (int64_t)vt.size(), deg, d_hbase, d_Ebase, d_dmax,
-                                                                   d_E, d_cursor, d_ng, d_svbase, d_sv);
-    if (nrt > 0) {
-      k_co_tiles<<<grid_for(nrt, 256), 256, 0, s>>>(d_rt, nrt, d_sv, d_svbase, deg, d_tiles_of);
-      SCAN_TRY(exclusive_scan(d_tiles_of, d_tile_first, nrt, scan_ws, s));
-      k_co_fill<<<grid_for(NNZ / 512 + 1, 1, 1 << 16), 256, 0, s>>>(d_rt, nrt, d_tile_first, d_sv, d_svbase, d_nz, deg,
-                                                                    off_u, no_sim, d_coabs, d_cobase, d_vbase,
-                                                                    co_key, co_id);
+    SCAN_HIP_TRY(hipMemsetAsync(d_hist, 0, (size_t)hbase[G] * 4, s));
+    SCAN_HIP_TRY(hipMemsetAsync(d_cursor, 0, (size_t)hbase[G] * 4, s));
+    if (!vt.empty())
+      k_graph_hist<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, s>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
+                                                                         d_dmax, d_hist);
+    {
+      int64_t *P, *X, *XS, *ws;
+      SCAN_TRY(tmp.alloc(&P, hbase[G] + 1));
+      SCAN_TRY(tmp.alloc(&X, std::max<int64_t>(segbase[G], 1)));
+      SCAN_TRY(tmp.alloc(&XS, segbase[G] + 1));
+      SCAN_TRY(tmp.alloc(&ws, scan_workspace_elems(std::max<int64_t>(hbase[G], segbase[G]))));
+      SCAN_TRY(exclusive_scan(d_hist, P, hbase[G], ws, s));
+      k_co_counts<<<grid_for(Ebase[G], 256), 256, 0, s>>>(P, d_hbase, d_Ebase, d_segbase, d_ng, G, d_E, X);
+      SCAN_TRY(exclusive_scan64(X, XS, segbase[G], ws, s));
+      k_co_offsets<<<grid_for(cobase[G], 256), 256, 0, s>>>(XS, d_cobase, d_segbase, d_ebase, d_hbase, d_hist, d_ng,
+                                                            G, d_corel, d_seg, d_nz);
     }
-    SCAN_TRY(segmented_sort(d_seg, (int64_t)seg.size() - 1, NNZ, co_key, co_id, co_thr, co_ids, s));
+    if (!vt.empty())
+      k_co_rank<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, s>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
+                                                                     d_Ebase, d_dmax, d_E, d_cursor, d_ng, d_vbase,
+                                                                     d_sv);
+    if (nrt > 0) {
+      k_co_tiles<<<grid_for(nrt, 256), 256, 0, s>>>(d_rt, nrt, d_sv, d_vbase, d_nz, deg, d_tiles_of);
+      SCAN_TRY(exclusive_scan(d_tiles_of, d_tile_first, nrt, scan_ws, s));
+      k_co_fill<<<grid_for(NNZ / 512 + 1, 1, 1 << 16), 256, 0, s>>>(d_rt, nrt, d_tile_first, d_sv, d_vbase, d_nz,
+                                                                    deg, off_u, no_sim, d_corel, d_cobase, d_ebase,
+                                                                    d_vbase, co_key, co_id);
+    }
+    SCAN_TRY(segmented_sort(d_seg, segbase[G], NNZ, co_key, co_id, co_thr, co_ids, s));
     SCAN_HIP_TRY(hipGetLastError());
     mark(5);
-    SCAN_HIP_TRY(hipStreamSynchronize(s));  // host-side tables above feed async copies
   } else {
-    for (int k = 2; k < 6; ++k) mark(k);
+    // no edges: every co_off is zero
+    SCAN_HIP_TRY(hipMemsetAsync(d_corel, 0, (size_t)cobase[G] * 8, s));
+    for (int k = 2; k < 7; ++k) mark(k);
   }
 
-  // Per-graph offsets (local) and core-order offsets, then the index views.
-  int64_t *off_local = off_u, *d_corel;
-  std::vector<int64_t> obase(G + 1, 0);
-  for (int32_t g = 0; g < G; ++g) obase[g + 1] = obase[g] + gs[g].n + 1;
+  // Per-graph offsets (local), then the index views.
+  int64_t *off_local = off_u;
   if (G > 1) {
-    int64_t *d_obase, *d_vb, *d_eb;
     SCAN_TRY(arena_alloc(*arena, &off_local, obase[G]));
-    SCAN_TRY(to_device(tmp, &d_obase, obase, s));
-    SCAN_TRY(to_device(tmp, &d_vb, vbase, s));
-    SCAN_TRY(to_device(tmp, &d_eb, ebase, s));
-    k_local_offsets<<<grid_for(obase[G], 256), 256, 0, s>>>(off_u, d_obase, d_vb, d_eb, G, obase[G], off_local);
+    k_local_offsets<<<grid_for(obase[G], 256), 256, 0, s>>>(off_u, d_obase, d_vbase, d_ebase, G, obase[G],
+                                                            off_local);
   }
-  SCAN_TRY(arena_alloc(*arena, &d_corel, cobase[G]));
-  SCAN_HIP_TRY(hipMemcpyAsync(d_corel, corel.data(), corel.size() * 8, hipMemcpyHostToDevice, s));
   SCAN_HIP_TRY(hipGetLastError());
+  // The temporaries are released in stream order; the host tables above must
+  // outlive their copy, which this wait guarantees.
   SCAN_HIP_TRY(hipStreamSynchronize(s));
 
   for (int32_t g = 0; g < G; ++g) {

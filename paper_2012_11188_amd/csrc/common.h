@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 #include <string>
@@ -68,24 +70,46 @@ void dev_free(void *p, size_t bytes, hipStream_t stream);
   } while (0)
 
 // A scoped group of device allocations released together (stream ordered).
+// Scoped device temporaries, released (stream-ordered) when the arena goes
+// out of scope. Small requests are carved from chunks of kChunk bytes, so a
+// build makes a handful of allocator calls rather than one per buffer (each
+// call may cross into the caller's allocator hook); large requests get their
+// own allocation. Offsets are 256-byte aligned.
 class DevArena {
  public:
+  static constexpr size_t kChunk = (size_t)32 << 20;
+  static constexpr size_t kAlign = 256;
   explicit DevArena(hipStream_t s) : stream_(s) {}
   ~DevArena() { release(); }
   DevArena(const DevArena &) = delete;
   DevArena &operator=(const DevArena &) = delete;
   template <class T>
   scan_status alloc(T **p, int64_t count) {
-    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    void *q = dev_alloc(bytes, stream_);
-    if (!q) return fail(SCAN_ENOMEM, "device allocation of %zu bytes failed", bytes);
-    items_[n_++] = {q, bytes};
-    *p = (T *)q;
+    const size_t bytes = ((size_t)(count > 0 ? count : 1) * sizeof(T) + kAlign - 1) & ~(kAlign - 1);
+    if (bytes >= kChunk / 4) {  // large: its own allocation
+      void *q = dev_alloc(bytes, stream_);
+      if (!q) return fail(SCAN_ENOMEM, "device allocation of %zu bytes failed", bytes);
+      items_.push_back({q, bytes});
+      *p = (T *)q;
+      return SCAN_OK;
+    }
+    if (used_ + bytes > cap_) {  // new chunk
+      void *q = dev_alloc(kChunk, stream_);
+      if (!q) return fail(SCAN_ENOMEM, "device allocation of %zu bytes failed", kChunk);
+      items_.push_back({q, kChunk});
+      cur_ = (unsigned char *)q;
+      used_ = 0;
+      cap_ = kChunk;
+    }
+    *p = (T *)(cur_ + used_);
+    used_ += bytes;
     return SCAN_OK;
   }
   void release() {
-    for (int i = 0; i < n_; ++i) dev_free(items_[i].p, items_[i].bytes, stream_);
-    n_ = 0;
+    for (auto &it : items_) dev_free(it.p, it.bytes, stream_);
+    items_.clear();
+    cur_ = nullptr;
+    used_ = cap_ = 0;
   }
 
  private:
@@ -94,8 +118,9 @@ class DevArena {
     size_t bytes;
   };
   hipStream_t stream_;
-  Item items_[64];
-  int n_ = 0;
+  std::vector<Item> items_;
+  unsigned char *cur_ = nullptr;
+  size_t used_ = 0, cap_ = 0;
 };
 
 // Grid size for grid-stride kernels.
@@ -116,10 +141,13 @@ scan_status exclusive_scan64(const int64_t *in, int64_t *out, int64_t n, int64_t
 
 // Sorts every segment [seg_off[i], seg_off[i+1]) of (key, id) by key
 // descending, id ascending (ids must be distinct within a segment). Reads
-// key_in/id_in, writes key_out/id_out (may not alias). Host-synchronising
-// (reads segment class sizes).
+// key_in/id_in, writes key_out/id_out (may not alias). Waits once for the
+// segment class sizes (they size the grids).
 scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
                            const double *key_in, const int32_t *id_in, double *key_out,
                            int32_t *id_out, hipStream_t s);
+// The same on host arrays, synchronous (diagnostic entry point).
+scan_status segmented_sort_values(const int64_t *seg_off, int64_t nseg, const double *keys,
+                                  const int32_t *ids, double *keys_out, int32_t *ids_out);
 
 }  // namespace scan

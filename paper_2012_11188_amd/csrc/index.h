@@ -18,10 +18,13 @@ struct IntersectConfig {
 };
 
 struct IntersectStats {
-  int32_t owners_small = 0;
-  int32_t chunks_big = 0;
   int32_t wbits = 0;
+  int32_t launches = 0;
+  // Optional pinned host int32[4]: receives (light vertices, bitmap chunks,
+  // -, heavy vertices) asynchronously, in stream order.
+  int32_t *host_counts = nullptr;
   hipEvent_t ev_start = nullptr;  // recorded after planning, before the first launch
+  hipEvent_t ev_mid = nullptr;    // recorded between the small- and large-owner launches
   hipEvent_t ev_end = nullptr;    // recorded after the last launch
 };
 
@@ -70,11 +73,13 @@ struct SharedArena {
 };
 
 // SCAN_PROFILE events of a build (shared by the indexes of a batch): start,
-// prepare, plan, intersect, neighbour order, core order.
+// prepare, plan, intersect, neighbour order, core order, and (6) the split
+// between the small- and large-owner intersection launches.
 struct BuildProfileEvents {
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t window_bits = 0;
   int32_t intersect_launches = 0;
-  int32_t owners = 0;
+  int32_t *plan_counts = nullptr;  // pinned int32[4], filled in stream order
   ~BuildProfileEvents();
 };
 

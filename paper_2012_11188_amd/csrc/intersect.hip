@@ -7,12 +7,12 @@
 // neighbour u streams its own, shorter row through it, so an edge costs
 // min-side work and no global atomics.
 //
-//   k_plan          one thread per vertex: owners with degree <= small_max go
-//                   to the small list, larger owners are cut into chunks of
-//                   `spc` row slots (wave-aggregated appends).
-//   k_small_owner   one wavefront per small owner: its row sits sorted in LDS;
-//                   a lower neighbour's row is streamed 64 ids at a time and
-//                   each id is located by a fixed-step binary search.
+//   k_plan          per vertex, by degree: 1..small_max go to the small list,
+//                   larger vertices are cut into chunks of `spc` row slots
+//                   (block-scanned appends, one reservation per tile).
+//   k_small_owner   one workgroup per small vertex: if it owns edges, its row
+//                   goes into an LDS hash table and its wavefronts stream the
+//                   lower neighbours' rows 64 ids at a time through it.
 //   k_big_owner     persistent workgroups (1024 threads) holding a bitmap of an
 //                   id window (2^wbits ids) in LDS: the owner's ids in the
 //                   window are set, every lower neighbour's ids in the window
@@ -20,6 +20,9 @@
 //                   cleared. Chunks are claimed from a global counter, edges
 //                   inside a chunk by wavefronts from an LDS counter.
 #include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstddef>
 
 #include "index.h"
 
@@ -75,50 +78,79 @@ struct BigChunk {
 };
 
 struct PlanCounts {
-  int32_t small;
+  int32_t small;       // vertices of degree 1..kLightDeg
   int32_t big;
-  int32_t counter;  // work counter of k_big_owner
-  int32_t pad;
+  int32_t counter;     // work counter of k_big_owner
+  int32_t heavy;       // vertices of degree kLightDeg+1..small_max
+  int32_t heavy_next;  // work counter of the heavy small-vertex kernel
+  int32_t pad[3];
 };
+
+constexpr int32_t kLightDeg = kWave;  // one wavefront per vertex up to this degree
 
 // ---------------------------------------------------------------------------
 // a2: ownership plan.
 
-__global__ __launch_bounds__(256) void k_plan(const int64_t *off, const int32_t *deg,
-                                              const int32_t *adj, int64_t n, int small_max,
-                                              int spc, int32_t *small_list, BigChunk *big_list,
-                                              PlanCounts *pc) {
-  const int lane = lane_id();
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n;
-       base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t h = base + threadIdx.x;
-    bool own = false;
-    int32_t dh = 0;
-    if (h < n) {
-      dh = deg[h];
-      const int64_t b = off[h];
-      for (int64_t s = b; s < b + dh; ++s) {
-        const int32_t u = adj[s];
-        if (is_lower(u, deg[u], (int32_t)h, dh)) {
-          own = true;
-          break;
-        }
-      }
+// Exclusive prefix sum over the workgroup (one value per thread, up to 1024
+// threads); *total receives the sum. wsum holds one int per wavefront.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int32_t *total) {
+  const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int32_t incl = wave_incl_sum(v);
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    const int32_t w = lane < nw ? wsum[lane] : 0;
+    const int32_t wi = wave_incl_sum(w);
+    if (lane < nw) wsum[lane] = wi - w;
+    if (lane == nw - 1) *total = wi;
+  }
+  __syncthreads();
+  return incl - v + wsum[wave];
+}
+
+constexpr int kPlanThreads = 256;
+constexpr int kPlanPer = 8;  // consecutive vertices per thread and tile
+
+// Tiles of kPlanThreads * kPlanPer vertices: a vertex of degree 1..small_max
+// goes to the small list, a larger one is cut into chunks of spc row slots.
+// Whether a vertex owns any edge is left to the intersection kernels (they
+// read the neighbour degrees anyway; a vertex that owns nothing costs one
+// staging pass). The block scans its counts, reserves list space with one
+// global atomic per list, and writes the entries in vertex order.
+__global__ __launch_bounds__(kPlanThreads) void k_plan(const int32_t *deg, int64_t n, int small_max,
+                                                       int spc, int32_t *small_list, int32_t *heavy_list,
+                                                       BigChunk *big_list, PlanCounts *pc) {
+  __shared__ int32_t wsum[kPlanThreads / kWave];
+  __shared__ int32_t tot_small, tot_heavy, tot_big, base_small, base_heavy, base_big;
+  constexpr int64_t kTile = (int64_t)kPlanThreads * kPlanPer;
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < n; t0 += (int64_t)gridDim.x * kTile) {
+    const int64_t v0 = t0 + (int64_t)threadIdx.x * kPlanPer;
+    int32_t code[kPlanPer];  // 0 nothing, -1 light, -2 heavy small, else number of chunks
+    int32_t ns = 0, nh = 0, nb = 0;
+#pragma unroll
+    for (int k = 0; k < kPlanPer; ++k) {
+      const int32_t dh = v0 + k < n ? deg[v0 + k] : 0;
+      code[k] = dh == 0 ? 0 : dh <= min(small_max, kLightDeg) ? -1 : dh <= small_max ? -2 : (dh + spc - 1) / spc;
+      ns += code[k] == -1;
+      nh += code[k] == -2;
+      nb += code[k] > 0 ? code[k] : 0;
     }
-    const bool small = own && dh <= small_max;
-    const uint64_t m = __ballot(small);
-    if (m) {
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      const int32_t sb =
-          __builtin_amdgcn_readlane(atomicAdd(&pc->small, lane == leader ? __popcll(m) : 0), leader);
-      if (small) small_list[sb + __popcll(m & lanes_below())] = (int32_t)h;
+    __syncthreads();  // wsum and the totals are reused across tiles
+    const int32_t os = block_excl_scan(ns, wsum, &tot_small);
+    const int32_t oh = block_excl_scan(nh, wsum, &tot_heavy);
+    const int32_t ob = block_excl_scan(nb, wsum, &tot_big);
+    if (threadIdx.x == 0) {
+      base_small = tot_small ? atomicAdd(&pc->small, tot_small) : 0;
+      base_heavy = tot_heavy ? atomicAdd(&pc->heavy, tot_heavy) : 0;
+      base_big = tot_big ? atomicAdd(&pc->big, tot_big) : 0;
     }
-    const int32_t nch = (own && !small) ? (dh + spc - 1) / spc : 0;
-    const int32_t incl = wave_incl_sum(nch);
-    const int32_t total = __shfl(incl, kWave - 1, kWave);
-    if (total) {
-      const int32_t bb = uniform(atomicAdd(&pc->big, lane == 0 ? total : 0));
-      for (int32_t k = 0; k < nch; ++k) big_list[bb + incl - nch + k] = BigChunk{(int32_t)h, k};
+    __syncthreads();
+    int32_t ps = base_small + os, ph = base_heavy + oh, pb = base_big + ob;
+#pragma unroll
+    for (int k = 0; k < kPlanPer; ++k) {
+      if (code[k] == -1) small_list[ps++] = (int32_t)(v0 + k);
+      if (code[k] == -2) heavy_list[ph++] = (int32_t)(v0 + k);
+      for (int32_t j = 0; j < code[k]; ++j) big_list[pb++] = BigChunk{(int32_t)(v0 + k), j};
     }
   }
 }
@@ -140,51 +172,125 @@ __device__ __forceinline__ void write_edge(int kind, int64_t s, int64_t mirror, 
 }
 
 // ---------------------------------------------------------------------------
-// Small owners: one wavefront (workgroup of 64) per owner.
+// Small owners (degree <= small_max): one workgroup per vertex, of one
+// wavefront up to degree kLightDeg and of kSmallWaves wavefronts above. The vertex's lower neighbours are compacted into LDS; if there
+// are any, its row goes into an LDS hash table (open addressing, load <= 1/2)
+// and the wavefronts take the lower neighbours in turn, streaming each one's
+// row 64 ids at a time and probing the table.
 
-__global__ __launch_bounds__(64) void k_small_owner(const int32_t *list, int32_t count,
-                                                    int small_max, const int64_t *off,
-                                                    const int32_t *deg, const int32_t *adj,
-                                                    int kind, double *sims, int32_t *counts) {
+constexpr int kSmallWaves = 4;
+constexpr int32_t kEmpty = -1;
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t x, int tbits) {
+  return ((uint32_t)x * 2654435761u) >> (32 - tbits);  // Fibonacci hashing
+}
+
+// LDS bytes of k_small_owner for a given small_max.
+static inline size_t small_lds_bytes(int small_max) {
+  int tb = 6;
+  while ((1 << tb) < 2 * small_max) ++tb;
+  return (size_t)small_max * 20 + ((size_t)4 << tb);
+}
+
+// One block per list entry, or (claim != nullptr) persistent blocks that
+// claim entries from a counter. The count is read from device memory.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
+    const int32_t *list, const int32_t *countp, int32_t *claim, int small_max, const int64_t *off,
+    const int32_t *deg, const int32_t *adj, int kind, double *sims, int32_t *counts) {
+  const int32_t count = *countp;
+  __shared__ int32_t s_idx;
   extern __shared__ unsigned char smem[];
-  int32_t *row = (int32_t *)smem;                  // [small_max]
-  int32_t *rdu = row + small_max;                  // [small_max] degree, -1 if not lower
-  int64_t *rou = (int64_t *)(rdu + small_max);     // [small_max]
-  const int lane = lane_id();
-  for (int32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+  int64_t *lou = (int64_t *)smem;               // [small_max] row offset of the j-th lower neighbour
+  int32_t *row = (int32_t *)(lou + small_max);  // [small_max] the vertex's row
+  int32_t *ldu = row + small_max;               // [small_max] degree of the j-th lower neighbour
+  int32_t *le = ldu + small_max;                // [small_max] its slot in the vertex's row
+  int32_t *tab = le + small_max;                // [2^tbits] hash table of the row
+  __shared__ int32_t s_nlow;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  for (int64_t idx0 = blockIdx.x;; idx0 += gridDim.x) {
+    int64_t idx = idx0;
+    if (WAVES > 1 && claim) {
+      __syncthreads();
+      if (threadIdx.x == 0) s_idx = atomicAdd(claim, 1);
+      __syncthreads();
+      idx = uniform(s_idx);
+    }
+    if (idx >= count) break;  // uniform across the block
     const int32_t h = list[idx];
     const int32_t dh = deg[h];
     const int64_t oh = off[h];
+    int tbits = 6;
+    while ((1 << tbits) < 2 * dh) ++tbits;
+    const int32_t tsize = 1 << tbits;
     __syncthreads();
-    for (int i = lane; i < dh; i += kWave) {
-      const int32_t u = adj[oh + i];
-      const int32_t d = deg[u];
-      row[i] = u;
-      rdu[i] = is_lower(u, d, h, dh) ? d : -1;
-      rou[i] = off[u];
+    if (threadIdx.x == 0) s_nlow = 0;
+    __syncthreads();
+    for (int32_t i0 = 0; i0 < dh; i0 += blockDim.x) {
+      const int32_t i = i0 + (int32_t)threadIdx.x;
+      int32_t u = 0, d = 0;
+      if (i < dh) {
+        u = adj[oh + i];
+        d = deg[u];
+        row[i] = u;
+      }
+      const bool low = i < dh && is_lower(u, d, h, dh);
+      const uint64_t m = __ballot(low);
+      int32_t base = 0;
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        base = __builtin_amdgcn_readlane(atomicAdd(&s_nlow, lane == leader ? __popcll(m) : 0), leader);
+      }
+      if (low) {
+        const int32_t j = base + __popcll(m & lanes_below());
+        le[j] = i;
+        ldu[j] = d;
+        lou[j] = off[u];
+      }
     }
     __syncthreads();
-    int top = 1;
-    while (top * 2 <= dh) top *= 2;
-    for (int e = 0; e < dh; ++e) {
-      const int32_t du = uniform(rdu[e]);
-      if (du < 0) continue;
-      const int64_t ou = uniform64(rou[e]);
+    const int32_t nlow = uniform(s_nlow);
+    if (nlow == 0) continue;  // owns no edge (uniform across the block)
+    for (int32_t i = threadIdx.x; i < tsize; i += blockDim.x) tab[i] = kEmpty;
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < dh; i += blockDim.x) {
+      const int32_t x = row[i];
+      uint32_t sl = hash_slot(x, tbits);
+      while (atomicCAS(&tab[sl], kEmpty, x) != kEmpty) sl = (sl + 1) & (uint32_t)(tsize - 1);
+    }
+    __syncthreads();
+    for (int32_t j = wave; j < nlow; j += WAVES) {
+      const int32_t du = uniform(ldu[j]);
+      const int64_t ou = uniform64(lou[j]);
+      const int32_t e = uniform(le[j]);
       int32_t t = 0;
       int64_t mpos = -1;
-      for (int32_t k0 = 0; k0 < du; k0 += kWave) {
-        const int32_t i = k0 + lane;
-        const bool valid = i < du;
-        const int32_t x = valid ? adj[ou + i] : -1;
-        int pos = -1;  // last index with row[pos] < x
-        for (int step = top; step > 0; step >>= 1) {
-          const int q = pos + step;
-          if (q < dh && row[q] < x) pos = q;
+      // Loads are clamped into the row (lanes past its end re-read its last
+      // id and are masked out), so they need no branch.
+      constexpr int UNROLL = 1;
+      for (int32_t k0 = 0; k0 < du; k0 += UNROLL * kWave) {
+        int32_t x[UNROLL];
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) x[k] = adj[ou + min(k0 + k * kWave + lane, du - 1)];
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+          const int32_t i = k0 + k * kWave + lane;
+          const bool valid = i < du;
+          uint32_t sl = hash_slot(x[k], tbits);
+          bool hit = false;
+          for (int32_t probe = 0; probe < tsize; ++probe) {  // ends at x or at an empty slot
+            const int32_t v = tab[sl];
+            if (v == x[k]) {
+              hit = true;
+              break;
+            }
+            if (v == kEmpty) break;
+            sl = (sl + 1) & (uint32_t)(tsize - 1);
+          }
+          t += __popcll(__ballot(valid && hit));
+          const uint64_t me = __ballot(valid && x[k] == h);
+          if (me) mpos = ou + k0 + k * kWave + (__ffsll((unsigned long long)me) - 1);
         }
-        const bool hit = valid && pos + 1 < dh && row[pos + 1] == x;
-        t += __popcll(__ballot(hit));
-        const uint64_t me = __ballot(valid && x == h);
-        if (me) mpos = ou + k0 + (__ffsll((unsigned long long)me) - 1);
       }
       // wave-uniform result: every lane stores the same values
       write_edge(kind, oh + e, mpos, t, du, dh, sims, counts);
@@ -229,23 +335,6 @@ __device__ __forceinline__ int64_t wave_lower_bound(const int32_t *row, int64_t 
   return lo + __popcll(__ballot(less));
 }
 
-// Exclusive prefix sum over the workgroup (one value per thread, up to 1024
-// threads); *total receives the sum. wsum holds one int per wavefront.
-__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int32_t *total) {
-  const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  const int32_t incl = wave_incl_sum(v);
-  if (lane == kWave - 1) wsum[wave] = incl;
-  __syncthreads();
-  if (wave == 0) {
-    const int32_t w = lane < nw ? wsum[lane] : 0;
-    const int32_t wi = wave_incl_sum(w);
-    if (lane < nw) wsum[lane] = wi - w;
-    if (lane == nw - 1) *total = wi;
-  }
-  __syncthreads();
-  return incl - v + wsum[wave];
-}
-
 // One workgroup per chunk (owner h, up to spc row slots), persistent over a
 // global chunk counter. Per id window: the owner's ids in the window are set
 // in the LDS bitmap; each lower neighbour's ids in the window are cut into
@@ -255,7 +344,7 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int
 // barrier that ends the window. Partial counts meet in LDS.
 template <bool kOneWindow>
 __global__ __launch_bounds__(kBigThreads) void k_big_owner(
-    const BigChunk *chunks, int32_t nchunks, PlanCounts *pc, int spc, int wbits, int64_t n,
+    const BigChunk *chunks, PlanCounts *pc, int spc, int wbits, int64_t n,
     const int64_t *off, const int32_t *deg, const int32_t *adj, int kind, double *sims,
     int32_t *counts) {
   extern __shared__ unsigned char smem[];
@@ -274,6 +363,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
   const int tid = threadIdx.x, lane = lane_id();
   constexpr bool one_window = kOneWindow;  // the whole id space fits one window
 
+  const int32_t nchunks = pc->big;  // written by k_plan: no host round trip
   for (int i = tid; i < nwords; i += blockDim.x) bm[i] = 0u;
   for (;;) {
     __syncthreads();
@@ -497,45 +587,67 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   if (big_lds_bytes(wbits, cfg.spc) > (size_t)lds_max) return fail(SCAN_EINVAL, "chunk size too large for LDS");
 
   DevArena tmp(s);
-  int32_t *small_list;
+  int32_t *small_list, *heavy_list;
   BigChunk *big_list;
   PlanCounts *pc;
   const int64_t big_cap = nnz / cfg.spc + n + 1;
   SCAN_TRY(tmp.alloc(&small_list, n));
+  SCAN_TRY(tmp.alloc(&heavy_list, n));
   SCAN_TRY(tmp.alloc(&big_list, big_cap));
   SCAN_TRY(tmp.alloc(&pc, 1));
   SCAN_HIP_TRY(hipMemsetAsync(pc, 0, sizeof(PlanCounts), s));
-  k_plan<<<grid_for(n, 256, 8192), 256, 0, s>>>(off, deg, adj, n, cfg.small_max, cfg.spc,
-                                                 small_list, big_list, pc);
+  k_plan<<<grid_for(n, kPlanThreads * kPlanPer, 2048), kPlanThreads, 0, s>>>(deg, n, cfg.small_max, cfg.spc, small_list,
+                                                 heavy_list, big_list, pc);
+  // The host reads the work counts to size the grids: one block per vertex
+  // lets the hardware balance the uneven rows, which persistent grids with a
+  // static split do not.
   PlanCounts h;
   SCAN_HIP_TRY(hipMemcpyAsync(&h, pc, sizeof(h), hipMemcpyDeviceToHost, s));
   SCAN_HIP_TRY(hipStreamSynchronize(s));
   if (stats) {
-    stats->owners_small = h.small;
-    stats->chunks_big = h.big;
     stats->wbits = wbits;
+    stats->launches = (h.small > 0) + (h.heavy > 0) + (h.big > 0);
+    if (stats->host_counts) {
+      stats->host_counts[0] = h.small;
+      stats->host_counts[1] = h.big;
+      stats->host_counts[3] = h.heavy;
+    }
     if (stats->ev_start) (void)hipEventRecord(stats->ev_start, s);
   }
-  if (h.small) {
-    size_t lds = (size_t)cfg.small_max * 16;
-    k_small_owner<<<grid_for(h.small, 1, 1 << 20), kWave, lds, s>>>(
-        small_list, h.small, cfg.small_max, off, deg, adj, kind, sims, counts);
+  if (h.small || h.heavy) {
+    const size_t lds = small_lds_bytes(cfg.small_max);
+    if (lds > (size_t)lds_max) return fail(SCAN_EINVAL, "small_max too large for LDS");
+    if (lds > 65536) {
+      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<kSmallWaves>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    if (h.heavy)  // the longer rows first
+      k_small_owner<kSmallWaves><<<h.heavy, kSmallWaves * kWave, lds, s>>>(
+          heavy_list, &pc->heavy, nullptr, cfg.small_max, off, deg, adj, kind, sims, counts);
+    if (h.small) {
+      const int cap = std::min<int>(cfg.small_max, kLightDeg);  // light rows: LDS sized for them
+      k_small_owner<1><<<h.small, kWave, small_lds_bytes(cap), s>>>(small_list, &pc->small, nullptr, cap, off,
+                                                                    deg, adj, kind, sims, counts);
+    }
     SCAN_HIP_TRY(hipGetLastError());
   }
+  if (stats && stats->ev_mid) (void)hipEventRecord(stats->ev_mid, s);
   if (h.big) {
     size_t lds = big_lds_bytes(wbits, cfg.spc);
     const bool one = n <= ((int64_t)1 << wbits);
     const void *fn = one ? (const void *)k_big_owner<true> : (const void *)k_big_owner<false>;
     if (lds > 65536)
       SCAN_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (size_t)lds_max / lds));
-    int grid = std::min<int64_t>((int64_t)cus * per_cu, h.big);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (size_t)lds_max / lds));
+    const int grid = (int)std::min<int64_t>((int64_t)cus * per_cu, h.big);
     if (one)
-      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, h.big, pc, cfg.spc, wbits, n, off,
-                                                       deg, adj, kind, sims, counts);
+      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj,
+                                                       kind, sims, counts);
     else
-      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, h.big, pc, cfg.spc, wbits, n, off,
-                                                        deg, adj, kind, sims, counts);
+      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj,
+                                                        kind, sims, counts);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);

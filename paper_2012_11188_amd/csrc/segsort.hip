@@ -129,46 +129,78 @@ __device__ __forceinline__ int passes_for(int64_t len) {
   return p;
 }
 
-// Wave-aggregated appends: one global atomic per (wavefront, class).
+// Segments are classified in tiles of kClassTile: a block counts its tile's
+// classes in LDS, reserves list space with one global atomic per class, then
+// places the segments (wave-aggregated LDS cursors). Few global atomics: a
+// per-wavefront reservation stalls on a handful of contended addresses.
+constexpr int kClassTile = 4096;
+
+__device__ __forceinline__ int seg_class(int64_t len) {
+  if (len <= 0) return -1;
+  return len <= 1 ? kClsCopy : len <= kWave ? kClsWave : len <= kSmallTile ? kClsSmall
+         : len <= kBigTile ? kClsMid : kClsBig;
+}
+
 __global__ __launch_bounds__(256) void k_classify(const int64_t *seg_off, int64_t nseg,
                                                   int32_t *lists, int64_t cap, SortStats *st,
                                                   int32_t *big_tiles_of) {
+  __shared__ int32_t cnt[kNumCls], base[kNumCls], cur[kNumCls];
+  __shared__ int32_t tiles_sum, passes_max;
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t below = (1ull << lane) - 1ull;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nseg;
-       base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    int c = -1;
-    int64_t len = 0;
-    if (i < nseg) {
-      len = seg_off[i + 1] - seg_off[i];
-      if (len > 0)
-        c = len <= 1 ? kClsCopy : len <= kWave ? kClsWave : len <= kSmallTile ? kClsSmall
-            : len <= kBigTile ? kClsMid : kClsBig;
+  for (int64_t t0 = (int64_t)blockIdx.x * kClassTile; t0 < nseg; t0 += (int64_t)gridDim.x * kClassTile) {
+    const int64_t t1 = min(nseg, t0 + kClassTile);
+    __syncthreads();
+    if (threadIdx.x < kNumCls) {
+      cnt[threadIdx.x] = 0;
+      cur[threadIdx.x] = 0;
     }
-    int32_t tiles = c == kClsBig ? (int32_t)((len + kBigTile - 1) / kBigTile) : 0;
-    for (int k = 0; k < kNumCls; ++k) {
-      const uint64_t m = __ballot(c == k);
-      if (!m) continue;
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      int32_t b = 0;
-      if (lane == leader) b = atomicAdd(&st->count[k], __popcll(m));
-      b = __shfl(b, leader, kWave);
-      if (c == k) {
-        const int pos = b + __popcll(m & below);
-        lists[k * cap + pos] = (int32_t)i;
-        if (k == kClsBig) big_tiles_of[pos] = tiles;
+    if (threadIdx.x == 0) {
+      tiles_sum = 0;
+      passes_max = 0;
+    }
+    __syncthreads();
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+      const int64_t len = seg_off[i + 1] - seg_off[i];
+      const int c = seg_class(len);
+      if (c >= 0) atomicAdd(&cnt[c], 1);
+      if (c == kClsBig) {
+        atomicAdd(&tiles_sum, (int32_t)((len + kBigTile - 1) / kBigTile));
+        atomicMax(&passes_max, passes_for(len));
       }
     }
-    if (c == kClsBig) {
-      atomicAdd(&st->big_tiles, tiles);
-      atomicMax(&st->max_passes, passes_for(len));
+    __syncthreads();
+    if (threadIdx.x < kNumCls && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&st->count[threadIdx.x], cnt[threadIdx.x]);
+    if (threadIdx.x == 0 && tiles_sum) {
+      atomicAdd(&st->big_tiles, tiles_sum);
+      atomicMax(&st->max_passes, passes_max);
+    }
+    __syncthreads();
+    for (int64_t b0 = t0; b0 < t1; b0 += blockDim.x) {
+      const int64_t i = b0 + threadIdx.x;
+      int64_t len = 0;
+      if (i < t1) len = seg_off[i + 1] - seg_off[i];
+      const int c = i < t1 ? seg_class(len) : -1;
+      for (int k = 0; k < kNumCls; ++k) {
+        const uint64_t m = __ballot(c == k);
+        if (!m) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        const int32_t b = __builtin_amdgcn_readlane(atomicAdd(&cur[k], lane == leader ? __popcll(m) : 0), leader);
+        if (c == k) {
+          const int32_t pos = base[k] + b + __popcll(m & below);
+          lists[k * cap + pos] = (int32_t)i;
+          if (k == kClsBig) big_tiles_of[pos] = (int32_t)((len + kBigTile - 1) / kBigTile);
+        }
+      }
     }
   }
 }
 
-__global__ void k_sort_copy(const int64_t *seg_off, const int32_t *list, int32_t count,
+// Class kernels read their segment counts (written by k_classify) from
+// device memory and run fixed grids, so the host never waits for them.
+__global__ void k_sort_copy(const int64_t *seg_off, const int32_t *list, const int32_t *countp,
                             const double *kin, const int32_t *iin, double *kout, int32_t *iout) {
+  const int32_t count = *countp;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t o = seg_off[list[i]];
@@ -205,9 +237,10 @@ __device__ __forceinline__ void wave_bitonic(uint64_t &k, int32_t &id, int lane)
 }
 
 __global__ __launch_bounds__(256) void k_sort_wave(const int64_t *seg_off, const int32_t *list,
-                                                   int32_t count, const double *kin,
+                                                   const int32_t *countp, const double *kin,
                                                    const int32_t *iin, double *kout,
                                                    int32_t *iout) {
+  const int32_t count = *countp;
   int lane = threadIdx.x & (kWave - 1);
   int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -228,64 +261,154 @@ __global__ __launch_bounds__(256) void k_sort_wave(const int64_t *seg_off, const
   }
 }
 
-// Bitonic network over n_pad (power of two) LDS elements, ascending.
-__device__ void block_bitonic(uint64_t *K, int32_t *I, int n_pad) {
-  for (int size = 2; size <= n_pad; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < n_pad / 2; i += blockDim.x) {
-        int lo = 2 * i - (i & (stride - 1));
-        int hi = lo + stride;
-        bool asc = (lo & size) == 0;
-        uint64_t ka = K[lo], kb = K[hi];
-        int32_t ia = I[lo], ib = I[hi];
-        bool gt = key_less(kb, ib, ka, ia);
-        if (gt == asc) {
-          K[lo] = kb;
-          K[hi] = ka;
-          I[lo] = ib;
-          I[hi] = ia;
+// Block merge sort of up to THREADS * ITEMS (key, id) pairs, ascending by
+// (key, id). Each thread sorts ITEMS pairs in registers (bitonic network),
+// then log2(THREADS) merge stages through LDS: in each, every thread finds
+// where its ITEMS outputs start on the merge path of its two input runs
+// (binary search) and merges them serially. Global loads and stores are
+// striped (coalesced) and pass through LDS. LDS indices are padded by one
+// slot per 16 so that the blocked runs of consecutive threads start on
+// different banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+template <int THREADS, int ITEMS>
+struct BlockSort {
+  static constexpr int N = THREADS * ITEMS;
+  static constexpr int NP = N + N / 16;
+  struct Smem {
+    uint64_t K[NP];
+    int32_t I[NP];
+  };
+
+  __device__ static void thread_sort(uint64_t (&k)[ITEMS], int32_t (&id)[ITEMS]) {
+#pragma unroll
+    for (int size = 2; size <= ITEMS; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const bool asc = (i & size) == 0;
+            const bool sw = asc ? key_less(k[j], id[j], k[i], id[i]) : key_less(k[i], id[i], k[j], id[j]);
+            const uint64_t ki = k[i], kj = k[j];
+            const int32_t ii = id[i], ij = id[j];
+            k[i] = sw ? kj : ki;
+            k[j] = sw ? ki : kj;
+            id[i] = sw ? ij : ii;
+            id[j] = sw ? ii : ij;
+          }
         }
       }
     }
   }
-  __syncthreads();
-}
 
-template <int TILE>
-__global__ __launch_bounds__(kSortBlock) void k_sort_block(const int64_t *seg_off,
-                                                           const int32_t *list, int32_t count,
-                                                           const double *kin, const int32_t *iin,
-                                                           double *kout, int32_t *iout) {
-  __shared__ uint64_t K[TILE];
-  __shared__ int32_t I[TILE];
-  for (int64_t b = blockIdx.x; b < count; b += gridDim.x) {
-    int64_t o = seg_off[list[b]];
-    int len = (int)(seg_off[list[b] + 1] - o);
-    int n_pad = 1;
-    while (n_pad < len) n_pad <<= 1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
-      if (i < len) {
-        K[i] = desc_key(kin[o + i]);
-        I[i] = iin[o + i];
-      } else {
-        K[i] = kPadKey;
-        I[i] = kPadId;
+  // Registers (blocked: thread t holds positions [t*ITEMS, (t+1)*ITEMS)) of
+  // sorted runs of width ITEMS -> one sorted run of N, blocked.
+  __device__ static void merge_stages(Smem &s, uint64_t (&k)[ITEMS], int32_t (&id)[ITEMS]) {
+    const int o = threadIdx.x * ITEMS;
+#pragma unroll 1
+    for (int w = ITEMS; w < N; w <<= 1) {
+#pragma unroll
+      for (int x = 0; x < ITEMS; ++x) {
+        s.K[lds_pad(o + x)] = k[x];
+        s.I[lds_pad(o + x)] = id[x];
       }
+      __syncthreads();
+      const int a0 = o & ~(2 * w - 1), b0 = a0 + w, diag = o - a0;
+      int lo = diag > w ? diag - w : 0, hi = diag < w ? diag : w;
+      while (lo < hi) {  // A elements among the first diag outputs
+        const int mid = (lo + hi) >> 1;
+        const int jb = lds_pad(b0 + diag - mid - 1), ja = lds_pad(a0 + mid);
+        if (key_less(s.K[jb], s.I[jb], s.K[ja], s.I[ja])) hi = mid;
+        else lo = mid + 1;
+      }
+      int ia = lo, ib = diag - lo;
+#pragma unroll
+      for (int x = 0; x < ITEMS; ++x) {
+        const int pa = lds_pad(a0 + min(ia, w - 1)), pb = lds_pad(b0 + min(ib, w - 1));
+        const uint64_t ka = s.K[pa], kb = s.K[pb];
+        const int32_t ra = s.I[pa], rb = s.I[pb];
+        const bool take_b = ib < w && (ia >= w || key_less(kb, rb, ka, ra));
+        k[x] = take_b ? kb : ka;
+        id[x] = take_b ? rb : ra;
+        ib += take_b ? 1 : 0;
+        ia += take_b ? 0 : 1;
+      }
+      __syncthreads();
     }
-    block_bitonic(K, I, n_pad);
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
-      kout[o + i] = key_to_sim(K[i]);
-      iout[o + i] = I[i];
+  }
+
+  // Sorts in[0, len) (len <= N; keys from load(i)), then store(i, key, id)
+  // for i < len. Starts and ends with all threads past a barrier.
+  template <class Load, class Store>
+  __device__ static void run(Smem &s, int len, Load load, Store store) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int x = 0; x < ITEMS; ++x) {
+      const int i = x * THREADS + t;
+      uint64_t key = kPadKey;
+      int32_t idv = kPadId;
+      if (i < len) load(i, key, idv);
+      s.K[lds_pad(i)] = key;
+      s.I[lds_pad(i)] = idv;
     }
+    __syncthreads();
+    uint64_t k[ITEMS];
+    int32_t id[ITEMS];
+#pragma unroll
+    for (int x = 0; x < ITEMS; ++x) {
+      k[x] = s.K[lds_pad(t * ITEMS + x)];
+      id[x] = s.I[lds_pad(t * ITEMS + x)];
+    }
+    __syncthreads();
+    thread_sort(k, id);
+    merge_stages(s, k, id);
+#pragma unroll
+    for (int x = 0; x < ITEMS; ++x) {
+      s.K[lds_pad(t * ITEMS + x)] = k[x];
+      s.I[lds_pad(t * ITEMS + x)] = id[x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < ITEMS; ++x) {
+      const int i = x * THREADS + t;
+      if (i < len) store(i, s.K[lds_pad(i)], s.I[lds_pad(i)]);
+    }
+    __syncthreads();
+  }
+};
+
+// One block per segment of the class (len <= THREADS * ITEMS).
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_sort_block(const int64_t *seg_off, const int32_t *list,
+                                                        const int32_t *countp, const double *kin,
+                                                        const int32_t *iin, double *kout,
+                                                        int32_t *iout) {
+  const int32_t count = *countp;
+  using BS = BlockSort<THREADS, ITEMS>;
+  __shared__ typename BS::Smem sm;
+  for (int64_t b = blockIdx.x; b < count; b += gridDim.x) {
+    const int64_t o = seg_off[list[b]];
+    const int len = (int)(seg_off[list[b] + 1] - o);
+    BS::run(
+        sm, len,
+        [&](int i, uint64_t &k, int32_t &id) {
+          k = desc_key(kin[o + i]);
+          id = iin[o + i];
+        },
+        [&](int i, uint64_t k, int32_t id) {
+          kout[o + i] = key_to_sim(k);
+          iout[o + i] = id;
+        });
   }
 }
 
 // Big segments: tile_seg[t] = index into the big list; tile_first[b] = first
 // global tile of big segment b.
-__global__ void k_big_tiles(const int32_t *big_tiles_of, const int64_t *tile_first, int32_t nbig,
+__global__ void k_big_tiles(const int32_t *big_tiles_of, const int64_t *tile_first, const int32_t *nbigp,
                             int32_t *tile_seg) {
+  const int32_t nbig = *nbigp;
   for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x)
     for (int64_t t = threadIdx.x; t < big_tiles_of[b]; t += blockDim.x)
       tile_seg[tile_first[b] + t] = (int32_t)b;
@@ -293,48 +416,56 @@ __global__ void k_big_tiles(const int32_t *big_tiles_of, const int64_t *tile_fir
 
 __global__ __launch_bounds__(kSortBlock) void k_big_tile_sort(
     const int64_t *seg_off, const int32_t *big_list, const int32_t *tile_seg,
-    const int64_t *tile_first, int64_t ntiles, const double *kin, const int32_t *iin,
+    const int64_t *tile_first, const int32_t *ntilesp, const double *kin, const int32_t *iin,
     uint64_t *KA, int32_t *IA) {
-  __shared__ uint64_t K[kBigTile];
-  __shared__ int32_t I[kBigTile];
+  const int64_t ntiles = *ntilesp;
+  using BS = BlockSort<kSortBlock, kBigTile / kSortBlock>;
+  __shared__ typename BS::Smem sm;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int32_t b = tile_seg[t];
-    int64_t seg = big_list[b];
-    int64_t o = seg_off[seg];
-    int64_t len = seg_off[seg + 1] - o;
-    int64_t start = (t - tile_first[b]) * kBigTile;
-    int cnt = (int)min((int64_t)kBigTile, len - start);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kBigTile; i += blockDim.x) {
-      if (i < cnt) {
-        K[i] = desc_key(kin[o + start + i]);
-        I[i] = iin[o + start + i];
-      } else {
-        K[i] = kPadKey;
-        I[i] = kPadId;
-      }
-    }
-    block_bitonic(K, I, kBigTile);
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-      KA[o + start + i] = K[i];
-      IA[o + start + i] = I[i];
-    }
+    const int32_t b = tile_seg[t];
+    const int64_t seg = big_list[b];
+    const int64_t o = seg_off[seg];
+    const int64_t len = seg_off[seg + 1] - o;
+    const int64_t start = o + (t - tile_first[b]) * kBigTile;
+    const int cnt = (int)min((int64_t)kBigTile, len - (start - o));
+    BS::run(
+        sm, cnt,
+        [&](int i, uint64_t &k, int32_t &id) {
+          k = desc_key(kin[start + i]);
+          id = iin[start + i];
+        },
+        [&](int i, uint64_t k, int32_t id) {
+          KA[start + i] = k;
+          IA[start + i] = id;
+        });
   }
 }
 
 // Number of elements taken from A among the first `o` outputs of merging
-// sorted A (la) and B (lb); elements are distinct.
-__device__ __forceinline__ int64_t co_rank(const uint64_t *KA, const int32_t *IA, int64_t la,
-                                           const uint64_t *KB, const int32_t *IB, int64_t lb,
-                                           int64_t o) {
+// sorted A (la) and B (lb); elements are distinct. The smallest i with
+// B[o-i-1] < A[i] (or the upper end of the range), found by one wavefront
+// 64 candidates at a time; every lane returns it.
+__device__ __forceinline__ int64_t wave_co_rank(const uint64_t *KA, const int32_t *IA, int64_t la,
+                                                const uint64_t *KB, const int32_t *IB, int64_t lb,
+                                                int64_t o) {
+  const int lane = threadIdx.x & (kWave - 1);
   int64_t lo = o > lb ? o - lb : 0, hi = o < la ? o : la;
   while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    int64_t j = o - mid - 1;
-    if (key_less(KB[j], IB[j], KA[mid], IA[mid]))
-      hi = mid;
-    else
-      lo = mid + 1;
+    // (kWave - 1) * step >= hi - lo: the last lane samples at or past hi
+    const int64_t step = (hi - lo + kWave - 2) / (kWave - 1);
+    const int64_t p = lo + (int64_t)lane * step;
+    bool t = true;  // positions at or past hi count as true
+    if (p < hi) {
+      const int64_t j = o - p - 1;
+      t = key_less(KB[j], IB[j], KA[p], IA[p]);
+    }
+    const uint64_t m = __ballot(t);  // nonzero: the last lane samples at or past hi
+    const int f = __ffsll((unsigned long long)m) - 1;
+    if (f == 0) return lo;
+    const int64_t nlo = lo + (int64_t)(f - 1) * step + 1;
+    const int64_t nhi = min(hi, lo + (int64_t)f * step);
+    lo = nlo;
+    hi = nhi;
   }
   return lo;
 }
@@ -345,10 +476,13 @@ __device__ __forceinline__ int64_t co_rank(const uint64_t *KA, const int32_t *IA
 // i is odd, else B; writes B / A, or the final output when i == P.
 __global__ __launch_bounds__(kSortBlock) void k_big_merge(
     const int64_t *seg_off, const int32_t *big_list, const int32_t *tile_seg,
-    const int64_t *tile_first, int64_t ntiles, int q, int max_passes, uint64_t *KA, int32_t *IA,
-    uint64_t *KB, int32_t *IB, double *kout, int32_t *iout) {
-  __shared__ uint64_t K[kBigTile];
-  __shared__ int32_t I[kBigTile];
+    const int64_t *tile_first, const int32_t *ntilesp, int q, const int32_t *max_passesp, uint64_t *KA,
+    int32_t *IA, uint64_t *KB, int32_t *IB, double *kout, int32_t *iout) {
+  const int max_passes = *max_passesp;
+  if (q > max_passes) return;  // launched against an upper bound on the passes
+  const int64_t ntiles = *ntilesp;
+  __shared__ uint64_t K[kBigTile + kBigTile / 16];  // padded indices (lds_pad)
+  __shared__ int32_t I[kBigTile + kBigTile / 16];
   __shared__ int64_t bounds[4];
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     int32_t b = tile_seg[t];
@@ -377,25 +511,26 @@ __global__ __launch_bounds__(kSortBlock) void k_big_merge(
     int64_t ostart = tstart - a0;
     int cnt = (int)min((int64_t)kBigTile, len - tstart);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t i0 = co_rank(AK, AI, la, BK, BI, lb, ostart);
-      int64_t i1 = co_rank(AK, AI, la, BK, BI, lb, ostart + cnt);
-      bounds[0] = i0;
-      bounds[1] = i1;
-      bounds[2] = ostart - i0;
-      bounds[3] = ostart + cnt - i1;
+    const int wave = threadIdx.x / kWave;
+    if (wave < 2) {  // wave 0: where this tile's outputs start, wave 1: end
+      const int64_t oo = wave == 0 ? ostart : ostart + cnt;
+      const int64_t r = wave_co_rank(AK, AI, la, BK, BI, lb, oo);
+      if ((threadIdx.x & (kWave - 1)) == 0) {
+        bounds[wave] = r;
+        bounds[2 + wave] = oo - r;
+      }
     }
     __syncthreads();
     int64_t i0 = bounds[0], i1 = bounds[1], j0 = bounds[2], j1 = bounds[3];
     int na = (int)(i1 - i0), nb = (int)(j1 - j0);
     // Stage A[i0, i1) at K[0, na) and B[j0, j1) at K[na, na + nb).
     for (int x = threadIdx.x; x < na; x += blockDim.x) {
-      K[x] = AK[i0 + x];
-      I[x] = AI[i0 + x];
+      K[lds_pad(x)] = AK[i0 + x];
+      I[lds_pad(x)] = AI[i0 + x];
     }
     for (int x = threadIdx.x; x < nb; x += blockDim.x) {
-      K[na + x] = BK[j0 + x];
-      I[na + x] = BI[j0 + x];
+      K[lds_pad(na + x)] = BK[j0 + x];
+      I[lds_pad(na + x)] = BI[j0 + x];
     }
     __syncthreads();
     uint64_t rk[kMergeItems];
@@ -406,8 +541,8 @@ __global__ __launch_bounds__(kSortBlock) void k_big_merge(
       int lo = my0 > nb ? my0 - nb : 0, hi = my0 < na ? my0 : na;
       while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        int j = my0 - mid - 1;
-        if (key_less(K[na + j], I[na + j], K[mid], I[mid]))
+        const int pj = lds_pad(na + my0 - mid - 1), pm = lds_pad(mid);
+        if (key_less(K[pj], I[pj], K[pm], I[pm]))
           hi = mid;
         else
           lo = mid + 1;
@@ -415,40 +550,38 @@ __global__ __launch_bounds__(kSortBlock) void k_big_merge(
       int ia = lo, ib = my0 - lo;
 #pragma unroll
       for (int x = 0; x < kMergeItems; ++x) {
-        bool takeA = ib >= nb || (ia < na && key_less(K[ia], I[ia], K[na + ib], I[na + ib]));
-        if (takeA) {
-          rk[x] = K[ia];
-          ri[x] = I[ia];
-          ++ia;
-        } else if (ib < nb) {
-          rk[x] = K[na + ib];
-          ri[x] = I[na + ib];
-          ++ib;
-        } else {
-          rk[x] = kPadKey;
-          ri[x] = kPadId;
-        }
+        // clamped to staged entries; a side that is exhausted is not used
+        const int pa = lds_pad(na > 0 ? min(ia, na - 1) : 0);
+        const int pb = lds_pad(nb > 0 ? na + min(ib, nb - 1) : 0);
+        const uint64_t ka = K[pa], kb = K[pb];
+        const int32_t ra = I[pa], rb = I[pb];
+        const bool has_a = ia < na, has_b = ib < nb;
+        const bool take_a = has_a && (!has_b || key_less(ka, ra, kb, rb));
+        rk[x] = take_a ? ka : has_b ? kb : kPadKey;
+        ri[x] = take_a ? ra : has_b ? rb : kPadId;
+        ia += take_a ? 1 : 0;
+        ib += (!take_a && has_b) ? 1 : 0;
       }
     }
     __syncthreads();
     if (my0 < cnt) {
 #pragma unroll
       for (int x = 0; x < kMergeItems; ++x) {
-        K[my0 + x] = rk[x];
-        I[my0 + x] = ri[x];
+        K[lds_pad(my0 + x)] = rk[x];
+        I[lds_pad(my0 + x)] = ri[x];
       }
     }
     __syncthreads();
     int64_t gbase = o + tstart;
     if (last) {
       for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
-        kout[gbase + x] = key_to_sim(K[x]);
-        iout[gbase + x] = I[x];
+        kout[gbase + x] = key_to_sim(K[lds_pad(x)]);
+        iout[gbase + x] = I[lds_pad(x)];
       }
     } else {
       for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
-        dK[gbase + x] = K[x];
-        dI[gbase + x] = I[x];
+        dK[gbase + x] = K[lds_pad(x)];
+        dI[gbase + x] = I[lds_pad(x)];
       }
     }
   }
@@ -465,25 +598,28 @@ scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
   SCAN_TRY(arena.alloc(&big_tiles_of, nseg));
   SCAN_TRY(arena.alloc(&st, 1));
   SCAN_HIP_TRY(hipMemsetAsync(st, 0, sizeof(SortStats), s));
-  k_classify<<<grid_for(nseg, 256), 256, 0, s>>>(seg_off, nseg, lists, nseg, st, big_tiles_of);
+  k_classify<<<grid_for(nseg, kClassTile, 2048), 256, 0, s>>>(seg_off, nseg, lists, nseg, st, big_tiles_of);
+  // The host reads the class sizes to size each grid (one block or wavefront
+  // per segment, which the hardware balances).
   SortStats h;
   SCAN_HIP_TRY(hipMemcpyAsync(&h, st, sizeof(SortStats), hipMemcpyDeviceToHost, s));
   SCAN_HIP_TRY(hipStreamSynchronize(s));
+  const int32_t *cnt = st->count;  // device copies of the class sizes
   if (h.count[kClsCopy])
-    k_sort_copy<<<grid_for(h.count[kClsCopy], 256), 256, 0, s>>>(
-        seg_off, lists + kClsCopy * nseg, h.count[kClsCopy], key_in, id_in, key_out, id_out);
+    k_sort_copy<<<grid_for(h.count[kClsCopy], 256), 256, 0, s>>>(seg_off, lists + kClsCopy * nseg, cnt + kClsCopy,
+                                                                 key_in, id_in, key_out, id_out);
   if (h.count[kClsWave])
     k_sort_wave<<<grid_for((int64_t)h.count[kClsWave] * kWave, 256), 256, 0, s>>>(
-        seg_off, lists + kClsWave * nseg, h.count[kClsWave], key_in, id_in, key_out, id_out);
+        seg_off, lists + kClsWave * nseg, cnt + kClsWave, key_in, id_in, key_out, id_out);
   if (h.count[kClsSmall])
-    k_sort_block<kSmallTile><<<grid_for(h.count[kClsSmall], 1), kSortBlock, 0, s>>>(
-        seg_off, lists + kClsSmall * nseg, h.count[kClsSmall], key_in, id_in, key_out, id_out);
+    k_sort_block<64, kSmallTile / 64><<<grid_for(h.count[kClsSmall], 1), 64, 0, s>>>(
+        seg_off, lists + kClsSmall * nseg, cnt + kClsSmall, key_in, id_in, key_out, id_out);
   if (h.count[kClsMid])
-    k_sort_block<kBigTile><<<grid_for(h.count[kClsMid], 1), kSortBlock, 0, s>>>(
-        seg_off, lists + kClsMid * nseg, h.count[kClsMid], key_in, id_in, key_out, id_out);
+    k_sort_block<kSortBlock, kBigTile / kSortBlock><<<grid_for(h.count[kClsMid], 1), kSortBlock, 0, s>>>(
+        seg_off, lists + kClsMid * nseg, cnt + kClsMid, key_in, id_in, key_out, id_out);
   if (h.count[kClsBig]) {
-    int32_t nbig = h.count[kClsBig];
-    int64_t ntiles = h.big_tiles;
+    const int32_t nbig = h.count[kClsBig];
+    const int64_t ntiles = h.big_tiles;
     int64_t *tile_first, *scan_ws;
     int32_t *tile_seg, *IA, *IB;
     uint64_t *KA, *KB;
@@ -496,16 +632,40 @@ scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
     SCAN_TRY(arena.alloc(&IB, total));
     SCAN_TRY(exclusive_scan(big_tiles_of, tile_first, nbig, scan_ws, s));
     const int32_t *big_list = lists + kClsBig * nseg;
-    k_big_tiles<<<grid_for(nbig, 1, 4096), 256, 0, s>>>(big_tiles_of, tile_first, nbig, tile_seg);
-    k_big_tile_sort<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(
-        seg_off, big_list, tile_seg, tile_first, ntiles, key_in, id_in, KA, IA);
+    k_big_tiles<<<grid_for(nbig, 1, 4096), 256, 0, s>>>(big_tiles_of, tile_first, cnt + kClsBig, tile_seg);
+    k_big_tile_sort<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
+                                                               &st->big_tiles, key_in, id_in, KA, IA);
     for (int q = 1; q <= h.max_passes; ++q)
-      k_big_merge<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg,
-                                                               tile_first, ntiles, q,
-                                                               h.max_passes, KA, IA, KB, IB,
-                                                               key_out, id_out);
+      k_big_merge<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
+                                                             &st->big_tiles, q, &st->max_passes, KA, IA, KB, IB,
+                                                             key_out, id_out);
   }
   SCAN_HIP_TRY(hipGetLastError());
+  return SCAN_OK;
+}
+
+scan_status segmented_sort_values(const int64_t *seg_off, int64_t nseg, const double *keys,
+                                  const int32_t *ids, double *keys_out, int32_t *ids_out) {
+  const int64_t total = seg_off[nseg];
+  hipStream_t s = nullptr;
+  DevArena tmp(s);
+  int64_t *d_off;
+  double *d_k, *d_ko;
+  int32_t *d_i, *d_io;
+  SCAN_TRY(tmp.alloc(&d_off, nseg + 1));
+  SCAN_TRY(tmp.alloc(&d_k, std::max<int64_t>(total, 1)));
+  SCAN_TRY(tmp.alloc(&d_ko, std::max<int64_t>(total, 1)));
+  SCAN_TRY(tmp.alloc(&d_i, std::max<int64_t>(total, 1)));
+  SCAN_TRY(tmp.alloc(&d_io, std::max<int64_t>(total, 1)));
+  SCAN_HIP_TRY(hipMemcpyAsync(d_off, seg_off, (nseg + 1) * 8, hipMemcpyHostToDevice, s));
+  if (total > 0) {
+    SCAN_HIP_TRY(hipMemcpyAsync(d_k, keys, total * 8, hipMemcpyHostToDevice, s));
+    SCAN_HIP_TRY(hipMemcpyAsync(d_i, ids, total * 4, hipMemcpyHostToDevice, s));
+    SCAN_TRY(segmented_sort(d_off, nseg, total, d_k, d_i, d_ko, d_io, s));
+    SCAN_HIP_TRY(hipMemcpyAsync(keys_out, d_ko, total * 8, hipMemcpyDeviceToHost, s));
+    SCAN_HIP_TRY(hipMemcpyAsync(ids_out, d_io, total * 4, hipMemcpyDeviceToHost, s));
+  }
+  SCAN_HIP_TRY(hipStreamSynchronize(s));
   return SCAN_OK;
 }
 

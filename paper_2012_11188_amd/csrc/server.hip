@@ -9,7 +9,9 @@
 // its slot's pinned array. With use_graph the whole batch (descriptor upload,
 // kernels, result copies) is a HIP graph captured once per buffer and
 // replayed. A completer thread waits for batches in submission order, copies
-// each result to the caller's destination and frees the buffer. Requests that
+// each result to the caller's destination (results for pinned host memory
+// are copied there by the device directly; device destinations are written
+// by the kernels) and frees the buffer. Requests that
 // arrive while batches run are queued and admitted as buffers free up, so
 // several batches overlap on the device.
 #include <hip/hip_runtime.h>
@@ -39,6 +41,7 @@ struct Request {
   double eps;
   int32_t *dst;
   bool dst_on_device;
+  bool dst_pinned;  // host memory the device can write directly
   double *latency_ms;
   Clock::time_point t_submit;
 };
@@ -142,7 +145,8 @@ void launcher_loop(scan_server *s) {
     const int64_t n = s->ix->n;
     for (int32_t i = 0; i < count && n > 0 && e == hipSuccess; ++i)
       if (!b.reqs[i].dst_on_device)
-        e = hipMemcpyAsync(b.h_memb[i], b.d_memb[i], (size_t)n * 4, hipMemcpyDeviceToHost, b.stream);
+        e = hipMemcpyAsync(b.reqs[i].dst_pinned ? b.reqs[i].dst : b.h_memb[i], b.d_memb[i], (size_t)n * 4,
+                           hipMemcpyDeviceToHost, b.stream);
     if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
     lk.lock();
     if (e != hipSuccess) s->error = fail(SCAN_EDEVICE, "server batch launch: %s", hipGetErrorString(e));
@@ -166,7 +170,7 @@ void completer_loop(scan_server *s) {
     const int64_t n = s->ix->n;
     for (size_t i = 0; i < b.reqs.size(); ++i) {
       const Request &r = b.reqs[i];
-      if (n > 0 && !r.dst_on_device) std::memcpy(r.dst, b.h_memb[i], (size_t)n * 4);
+      if (n > 0 && !r.dst_on_device && !r.dst_pinned) std::memcpy(r.dst, b.h_memb[i], (size_t)n * 4);
       if (r.latency_ms)
         *r.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_submit).count();
     }
@@ -254,11 +258,19 @@ scan_status scan_server_submit_ex(scan_server *s, int32_t mu, double eps, int32_
   const Clock::time_point now = Clock::now();
   if (!s || !ticket || (!dst && s->ix->n > 0)) return fail(SCAN_EINVAL, "null argument");
   if (mu < 2 || std::isnan(eps)) return fail(SCAN_EINVAL, "invalid (mu, eps)");
+  bool pinned = false;
+  if (!dst_on_device && dst) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dst) == hipSuccess)
+      pinned = attr.type == hipMemoryTypeHost;
+    else
+      (void)hipGetLastError();  // pageable memory: not an error here
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->error != SCAN_OK) return fail(s->error, "server failed earlier");
   if (s->pending.size() >= s->pending_cap) return fail(SCAN_EBUSY, "server queue full");
   const uint64_t t = s->next_ticket++;
-  s->pending.push_back(Request{t, mu, eps, dst, dst_on_device != 0, latency_ms, now});
+  s->pending.push_back(Request{t, mu, eps, dst, dst_on_device != 0, pinned, latency_ms, now});
   s->state[t] = 0;
   *ticket = t;
   s->cv_launch.notify_one();

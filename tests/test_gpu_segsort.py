@@ -1,0 +1,84 @@
+"""The segmented sort behind the neighbour and core orders, through its
+diagnostic entry point: every segment sorted by key descending, ties by id
+ascending, for segment lengths across every size class of the sort (single
+elements, one wavefront, one block, one tile, several tiles merged in 1..5
+passes, with segments of different pass counts in one call), with many tied
+keys. Expected order: numpy's lexsort."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import paper_2012_11188_amd as scan
+from gpu_util import bits
+
+pytestmark = pytest.mark.gpu
+
+EDGE_LENGTHS = [0, 1, 2, 3, 63, 64, 65, 100, 511, 512, 513, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
+                12289, 16384, 16385, 18859, 18859, 18859, 33000, 70001, 131072]
+
+
+def make(lengths, seed, distinct_keys):
+    rng = np.random.default_rng(seed)
+    seg_off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    total = int(seg_off[-1])
+    grid = rng.random(distinct_keys) + 1e-3  # few distinct keys: many ties
+    keys = grid[rng.integers(0, distinct_keys, total)]
+    ids = np.empty(total, np.int32)
+    for i, ln in enumerate(lengths):
+        ids[seg_off[i]:seg_off[i + 1]] = rng.choice(max(4 * ln, 1), ln, replace=False)
+    return seg_off, keys, ids
+
+
+def expected(seg_off, keys, ids):
+    ko, io = np.empty_like(keys), np.empty_like(ids)
+    for i in range(len(seg_off) - 1):
+        b, e = seg_off[i], seg_off[i + 1]
+        p = np.lexsort((ids[b:e], -keys[b:e]))
+        ko[b:e], io[b:e] = keys[b:e][p], ids[b:e][p]
+    return ko, io
+
+
+@pytest.mark.parametrize("distinct", [3, 50, 10**6])
+def test_segsort_edge_lengths(distinct):
+    seg_off, keys, ids = make(EDGE_LENGTHS, seed=distinct, distinct_keys=distinct)
+    ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
+    wk, wi = expected(seg_off, keys, ids)
+    bad = np.flatnonzero(io != wi)
+    if len(bad):
+        seg = np.searchsorted(seg_off, bad[0], side="right") - 1
+        pytest.fail(f"{len(bad)} ids differ; first at {bad[0]} in segment {seg} of length "
+                    f"{seg_off[seg + 1] - seg_off[seg]}")
+    assert np.array_equal(bits(ko), bits(wk))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_segsort_random_mix(seed):
+    rng = np.random.default_rng(seed)
+    small = rng.integers(0, 80, 3000)
+    mid = rng.integers(65, 4097, 60)
+    big = rng.integers(4097, 40000, 12)
+    lengths = rng.permutation(np.concatenate([small, mid, big]))
+    seg_off, keys, ids = make(lengths, seed=seed, distinct_keys=int(rng.integers(2, 1000)))
+    ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
+    wk, wi = expected(seg_off, keys, ids)
+    assert np.array_equal(io, wi) and np.array_equal(bits(ko), bits(wk))
+
+
+def test_segsort_repeatable():
+    seg_off, keys, ids = make([18859] * 40 + [5000] * 20 + [70] * 500, seed=9, distinct_keys=40)
+    first = scan.scan_segmented_sort(seg_off, keys, ids)
+    for _ in range(3):
+        again = scan.scan_segmented_sort(seg_off, keys, ids)
+        assert np.array_equal(again[1], first[1])
+    assert np.array_equal(first[1], expected(seg_off, keys, ids)[1])
+
+
+def test_segsort_errors():
+    with pytest.raises(scan.ScanError):
+        scan.scan_segmented_sort(np.array([0, 2, 1]), np.ones(2), np.arange(2))
+    with pytest.raises(scan.ScanError):
+        scan.scan_segmented_sort(np.array([0, 2]), np.array([1.0, -1.0]), np.arange(2))
+    with pytest.raises(scan.ScanError):
+        scan.scan_segmented_sort(np.array([0, 1]), np.array([1.0]), np.array([2**31 - 1]))

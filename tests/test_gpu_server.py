@@ -54,11 +54,18 @@ def test_server_results(served, use_graph, slots, batch):
             dst = np.full(g.n, -7, np.int32)
             srv.wait(srv.submit(*r, dst))
             assert np.array_equal(dst, want[r]), r
-        # in the mix: everything at once, every third result kept in HBM
+        # in the mix: everything at once; results go to HBM, pinned host
+        # memory (written by the device directly) or pageable host memory
         import torch
 
-        dsts = [torch.full((g.n,), -7, dtype=torch.int32, device="cuda") if i % 3 == 1
-                else np.full(g.n, -7, np.int32) for i in range(len(reqs))]
+        def dst_for(i):
+            if i % 3 == 1:
+                return torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+            if i % 3 == 2:
+                return torch.full((g.n,), -7, dtype=torch.int32).pin_memory().numpy()
+            return np.full(g.n, -7, np.int32)
+
+        dsts = [dst_for(i) for i in range(len(reqs))]
         lat = np.full(len(reqs), -1.0)
         torch.cuda.synchronize()
         tickets = [srv.submit_ex(*r, d, lat.ctypes.data + 8 * i) for i, (r, d) in enumerate(zip(reqs, dsts))]

@@ -75,3 +75,25 @@ def test_degree_stats():
     assert st["dmax"] == 3 and st["edges"] == 5
     assert st["w_min"] == 2 + 2 + 3 + 2 + 2
     assert st["sum_deg2"] == 4 + 9 + 9 + 4
+
+
+def test_owner_split():
+    """The owner split partitions the edges and W_min; brute force on a small
+    graph with a threshold that lands in the middle of the degree range."""
+    g = graphgen.rmat(9, 8, seed=4)
+    deg = np.diff(g.off)
+    for small_max in (0, 3, 8, 10**6):
+        sp = graphgen.owner_split(g, small_max)
+        st = graphgen.degree_stats(g)
+        assert sp["edges_small"] + sp["edges_big"] == g.num_edges
+        assert sp["w_small"] + sp["w_big"] == st["w_min"]
+        es = ws = 0
+        for u in range(g.n):
+            for v in g.adj[g.off[u]:g.off[u + 1]]:
+                if v <= u:
+                    continue
+                owner = u if (deg[u], u) > (deg[v], v) else v
+                if deg[owner] <= small_max:
+                    es += 1
+                    ws += min(deg[u], deg[v])
+        assert (sp["edges_small"], sp["w_small"]) == (es, ws)

@@ -322,3 +322,32 @@ def test_direct_scan_random(n, p):
     for seed in range(8):
         g = graphgen.random_graph(n, p, seed=1000 * n + seed + int(100 * p))
         check_against_direct_scan(g, seed % 2)
+
+
+def test_neighbor_order_row_pins():
+    """One-row neighbour order: similarity descending, ties by lower id; the
+    full pass is the per-row function applied to every row."""
+    ids, sims = oracle.neighbor_order_row(np.array([5, 3, 9, 1]), np.array([0.5, 0.7, 0.5, 0.7]))
+    assert ids.tolist() == [1, 3, 5, 9] and sims.tolist() == [0.7, 0.7, 0.5, 0.5]
+    g = graphgen.random_graph(60, 0.2, seed=12)
+    ix = oracle.build_index(g)
+    for v in range(g.n):
+        a, b = g.off[v], g.off[v + 1]
+        ri, rs = oracle.neighbor_order_row(g.adj[a:b], ix.sim[a:b])
+        assert np.array_equal(ri, ix.no_ids[a:b]) and np.array_equal(rs, ix.no_sim[a:b])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_query_props_match_oracle(seed):
+    """The host-side query checker used at sizes beyond the oracle agrees with
+    the oracle's query on small graphs, over a grid of (mu, eps)."""
+    from query_props import expected_query
+
+    g = graphgen.sbm(600, 6, 0.08, 0.004, seed=seed) if seed < 3 else graphgen.rmat(9, 8, seed=seed)
+    ix = oracle.build_index(g)
+    for mu in (2, 3, 5, 9):
+        for eps in (0.1, 0.3, 0.5, 0.7):
+            memb, core = oracle.query(ix, mu, eps)
+            w, wc = expected_query(g.off, g.adj, ix.sim, ix.no_ids, ix.no_sim, mu, eps)
+            assert np.array_equal(wc, core.astype(bool)), (mu, eps)
+            assert np.array_equal(w, memb), (mu, eps)
