@@ -64,72 +64,56 @@ __device__ __forceinline__ int find_graph(const int64_t *base, int G, int64_t x)
 
 constexpr int kPrepThreads = 256;
 
-__global__ __launch_bounds__(kPrepThreads) void k_union_prepare(const GraphDesc *gd, const int64_t *item_base, int G,
-                                int64_t total, int copy_adj, int64_t *off_u, int32_t *deg_u,
-                                int32_t *adj_u, unsigned *dmax_g) {
-  // running maximum degree of the graph this thread last visited, flushed
-  // with one atomic per wavefront when all its lanes saw the same graph
-  int gl = -1;
-  unsigned ml = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int g = find_graph(item_base, G, i);
-    const GraphDesc d = gd[g];
-    const int64_t j = i - d.item_base;
-    if (j <= d.n) {
-      int64_t o, o1 = 0;
-      if (d.off_bits == 32) {
-        o = ((const int32_t *)d.off)[j];
-        if (j < d.n) o1 = ((const int32_t *)d.off)[j + 1];
-      } else {
-        o = ((const int64_t *)d.off)[j];
-        if (j < d.n) o1 = ((const int64_t *)d.off)[j + 1];
-      }
-      off_u[d.vbase + j] = d.ebase + o;
-      if (j < d.n) {
-        const int64_t deg = o1 - o;
-        deg_u[d.vbase + j] = (int32_t)deg;
-        if (g != gl) {
-          if (gl >= 0) atomicMax(&dmax_g[gl], ml);
-          gl = g;
-          ml = 0;
-        }
-        ml = max(ml, (unsigned)(deg > 0 ? deg : 0));
-      }
-    } else if (copy_adj) {
-      const int64_t s = j - (d.n + 1);
-      adj_u[d.ebase + s] = (int32_t)(d.vbase + d.adj[s]);
-    }
-  }
-  // Wavefronts whose lanes all saw one graph reduce in registers; the block
-  // then issues one atomic per run of waves with the same graph (usually one
-  // per block). Other lanes flush on their own (blocks at graph boundaries).
-  __shared__ int32_t wg[kPrepThreads / kWave];
-  __shared__ unsigned wm[kPrepThreads / kWave];
+// Work tiles of k_union_prepare: items [i0, i1) of graph g (its n+1 offsets,
+// then, when the adjacency is copied, its nnz ids), planned on the host so
+// that each tile lies in one graph.
+struct PrepTile {
+  int32_t g;
+  int32_t pad;
+  int64_t i0, i1;
+};
+constexpr int64_t kPrepTile = 4096;
+
+__global__ __launch_bounds__(kPrepThreads) void k_union_prepare(const GraphDesc *gd, const PrepTile *tiles,
+                                                                int64_t ntiles, int copy_adj, int64_t *off_u,
+                                                                int32_t *deg_u, int32_t *adj_u, unsigned *dmax_g) {
+  __shared__ unsigned wmax[kPrepThreads / kWave];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int g0 = __builtin_amdgcn_readfirstlane(gl);
-  const bool uni = __all(gl == g0);
-  unsigned m = ml;
-#pragma unroll
-  for (int k = kWave / 2; k > 0; k >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, k, kWave));
-  if (lane == 0) {
-    wg[wave] = uni ? g0 : -1;
-    wm[wave] = m;
-  }
-  if (!uni && gl >= 0) atomicMax(&dmax_g[gl], ml);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int cg = -1;
-    unsigned cm = 0;
-    for (int w = 0; w < kPrepThreads / kWave; ++w) {
-      if (wg[w] != cg) {
-        if (cg >= 0) atomicMax(&dmax_g[cg], cm);
-        cg = wg[w];
-        cm = 0;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const PrepTile tl = tiles[t];
+    const GraphDesc d = gd[tl.g];
+    unsigned ml = 0;  // the tile's maximum degree
+    for (int64_t j = tl.i0 + threadIdx.x; j < tl.i1; j += blockDim.x) {
+      if (j <= d.n) {
+        int64_t o, o1 = 0;
+        if (d.off_bits == 32) {
+          o = ((const int32_t *)d.off)[j];
+          if (j < d.n) o1 = ((const int32_t *)d.off)[j + 1];
+        } else {
+          o = ((const int64_t *)d.off)[j];
+          if (j < d.n) o1 = ((const int64_t *)d.off)[j + 1];
+        }
+        off_u[d.vbase + j] = d.ebase + o;
+        if (j < d.n) {
+          const int64_t deg = o1 - o;
+          deg_u[d.vbase + j] = (int32_t)deg;
+          ml = max(ml, (unsigned)(deg > 0 ? deg : 0));
+        }
+      } else if (copy_adj) {
+        const int64_t s = j - (d.n + 1);
+        adj_u[d.ebase + s] = (int32_t)(d.vbase + d.adj[s]);
       }
-      cm = max(cm, wm[w]);
     }
-    if (cg >= 0) atomicMax(&dmax_g[cg], cm);
+#pragma unroll
+    for (int k = kWave / 2; k > 0; k >>= 1) ml = max(ml, (unsigned)__shfl_xor((int)ml, k, kWave));
+    __syncthreads();  // wmax is reused across tiles
+    if (lane == 0) wmax[wave] = ml;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned m = 0;
+      for (int w = 0; w < kPrepThreads / kWave; ++w) m = max(m, wmax[w]);
+      if (m) atomicMax(&dmax_g[tl.g], m);
+    }
   }
 }
 
@@ -563,9 +547,15 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   if (copy_adj) SCAN_TRY(tmp.alloc(&adj_u, NNZ));
   else adj_u = const_cast<int32_t *>(hd[0].adj);
   GraphDesc *d_gd;
-  int64_t *d_item_base;
+  PrepTile *d_ptiles;
+  std::vector<PrepTile> ptiles;
+  for (int32_t g = 0; g < G; ++g) {
+    const int64_t items = item_base[g + 1] - item_base[g];
+    for (int64_t i0 = 0; i0 < items; i0 += kPrepTile)
+      ptiles.push_back(PrepTile{g, 0, i0, std::min(items, i0 + kPrepTile)});
+  }
   SCAN_TRY(to_device(tmp, &d_gd, hd, s));
-  SCAN_TRY(to_device(tmp, &d_item_base, item_base, s));
+  SCAN_TRY(to_device(tmp, &d_ptiles, ptiles, s));
   SCAN_HIP_TRY(hipMemsetAsync(d_dmax, 0, (size_t)G * 4, s));
   SCAN_HIP_TRY(hipMemsetAsync(off_u, 0, 8, s));
   {
@@ -588,8 +578,8 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       SCAN_HIP_TRY(hipStreamSynchronize(s));
     }
     if (total > 0)
-      k_union_prepare<<<grid_for(total, kPrepThreads, 1024), kPrepThreads, 0, s>>>(d_gd, d_item_base, G, total, copy_adj ? 1 : 0,
-                                                          off_u, deg, adj_u, d_dmax);
+      k_union_prepare<<<grid_for((int64_t)ptiles.size(), 1, 4096), kPrepThreads, 0, s>>>(
+          d_gd, d_ptiles, (int64_t)ptiles.size(), copy_adj ? 1 : 0, off_u, deg, adj_u, d_dmax);
   }
   if (flags & SCAN_VALIDATE) {
     int32_t *d_err;
