@@ -62,6 +62,30 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
   return v;
 }
 
+// Sum and maximum over the wavefront with DPP row shifts and row broadcasts
+// (register-path lane exchanges, no LDS crossbar): after row_shr 1, 2, 4, 8
+// each row's last lane holds the row total, row_bcast 15 and 31 carry the
+// totals to lane 63, which is read into a scalar. All lanes must be active.
+// For the maximum, lanes with no source read 0, so values must be >= 0.
+__device__ __forceinline__ int32_t dpp_wave_sum(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true);  // row_bcast:31 into rows 2, 3
+  return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+__device__ __forceinline__ int32_t dpp_wave_max_nonneg(int32_t v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true));
+  return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
 __device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
   const int lane = lane_id();
 #pragma unroll
@@ -524,11 +548,14 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
           fetch(x, adj + oua, (uint32_t)base, (uint32_t)hia);
           probe(x, (uint32_t)base, (uint32_t)hia, cnt, mpi);
         }
-        const int32_t t = wave_sum(cnt);
-        const int32_t mp = wave_max(mpi);
-        // t and mp are wave-uniform; lane 0 adds, every lane stores the mirror.
-        atomicAdd(&le_cnt[ea], lane == 0 ? t : 0);
-        if (mp >= 0) le_mir[ea] = oua + mp;
+        const int32_t t = dpp_wave_sum(cnt);
+        const int32_t mp = dpp_wave_max_nonneg(mpi + 1) - 1;
+        // t and mp are wave-uniform scalars: lane 0 records them (no return
+        // value is used, so no lane waits on another).
+        if (lane == 0) {
+          atomicAdd(&le_cnt[ea], t);
+          if (mp >= 0) le_mir[ea] = oua + mp;
+        }
         ea = eb;
         loa = lob;
         hia = hib;
