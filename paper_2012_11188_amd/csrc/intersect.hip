@@ -328,6 +328,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
 constexpr int kBigThreads = 1024;
 constexpr int kUnroll = 4;   // loads in flight per lane
 constexpr int kSeg = 1024;   // ids per work item (rows longer than this are split)
+constexpr int kRest = kSeg / kWave - kUnroll;  // loads per lane for the rest of a long item
 
 struct BigShared {
   int32_t chunk;
@@ -515,6 +516,16 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
           x[k] = row[q & vm];
         }
       };
+      // The same for the rest of a long item, all of whose loads are issued
+      // before any is used.
+      auto fetch_rest = [&](int32_t x[kRest], const int32_t *row, uint32_t base, uint32_t hi) {
+#pragma unroll
+        for (int k = 0; k < kRest; ++k) {
+          const uint32_t q = base + k * kWave + lane;
+          const uint32_t vm = 0u - (uint32_t)(q < hi);
+          x[k] = row[q & vm];
+        }
+      };
       auto probe = [&](const int32_t x[kUnroll], uint32_t base, uint32_t hi, int32_t &cnt,
                        int32_t &mpi) {
 #pragma unroll
@@ -530,6 +541,20 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
           mpi = eq ? (int32_t)q : mpi;
         }
       };
+      // A chunk with all kWave * kUnroll ids inside the item needs no masks
+      // (the branch between the two holds no loads).
+      auto probe_full = [&](const int32_t x[kUnroll], uint32_t base, int32_t &cnt, int32_t &mpi) {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          const uint32_t y = kOneWindow ? (uint32_t)x[k] : (uint32_t)(x[k] - (int32_t)w0);
+          cnt += (int32_t)((bm[y >> 5] >> (y & 31u)) & 1u);
+          mpi = x[k] == h ? (int32_t)(base + k * kWave + lane) : mpi;
+        }
+      };
+      auto probe_any = [&](const int32_t x[kUnroll], uint32_t base, uint32_t hi, int32_t &cnt, int32_t &mpi) {
+        if (base + kWave * kUnroll <= hi) probe_full(x, base, cnt, mpi);
+        else probe(x, base, hi, cnt, mpi);
+      };
       int32_t ea, loa, hia;
       int64_t oua;
       int32_t xa[kUnroll];
@@ -542,11 +567,22 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         claim(eb, lob, hib, oub);
         fetch(xb, adj + oub, (uint32_t)lob, (uint32_t)hib);
         int32_t cnt = 0, mpi = -1;
-        probe(xa, (uint32_t)loa, (uint32_t)hia, cnt, mpi);
-        for (int32_t base = loa + kWave * kUnroll; base < hia; base += kWave * kUnroll) {
-          int32_t x[kUnroll];
-          fetch(x, adj + oua, (uint32_t)base, (uint32_t)hia);
-          probe(x, (uint32_t)base, (uint32_t)hia, cnt, mpi);
+        probe_any(xa, (uint32_t)loa, (uint32_t)hia, cnt, mpi);
+        // The rest of the item (at most kSeg - kWave * kUnroll ids): one chunk
+        // if it fits, else all of it at once, so it costs one load latency.
+        const uint32_t r0 = (uint32_t)loa + kWave * kUnroll;
+        if (r0 < (uint32_t)hia) {
+          if ((uint32_t)hia - r0 <= kWave * kUnroll) {
+            int32_t x[kUnroll];
+            fetch(x, adj + oua, r0, (uint32_t)hia);
+            probe_any(x, r0, (uint32_t)hia, cnt, mpi);
+          } else {
+            int32_t x[kRest];
+            fetch_rest(x, adj + oua, r0, (uint32_t)hia);
+#pragma unroll
+            for (int c = 0; c < kRest / kUnroll; ++c)
+              probe_any(x + c * kUnroll, r0 + c * kWave * kUnroll, (uint32_t)hia, cnt, mpi);
+          }
         }
         const int32_t t = dpp_wave_sum(cnt);
         const int32_t mp = dpp_wave_max_nonneg(mpi + 1) - 1;
