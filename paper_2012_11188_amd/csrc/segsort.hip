@@ -113,8 +113,21 @@ scan_status exclusive_scan64(const int64_t *in, int64_t *out, int64_t n, int64_t
 constexpr int kSortBlock = 256;
 constexpr int kBigTile = 4096;
 constexpr int kMergeItems = kBigTile / kSortBlock;  // 16
-enum { kClsCopy = 0, kClsWave = 1, kClsSmall = 2, kClsMid = 3, kClsBig = 4, kNumCls = 5 };
-constexpr int kSmallTile = 512;
+// Segment length classes: single elements are copied; up to 64 elements,
+// lane groups of 8 / 16 / 32 / 64 sort one segment each (several segments
+// per wavefront); up to 4096, one workgroup per segment with a block sort of
+// the smallest fitting shape; longer segments are tiled and merged.
+enum {
+  kClsCopy = 0,
+  kClsW8, kClsW16, kClsW32, kClsW64,
+  kClsB128, kClsB256, kClsB512, kClsB1024, kClsB2048, kClsB4096,
+  kClsBig,
+  kNumCls
+};
+// Longest segment of a class (classes below kClsBig).
+__host__ __device__ constexpr int class_cap(int c) {
+  return c == kClsCopy ? 1 : c <= kClsW64 ? 8 << (c - kClsW8) : 128 << (c - kClsB128);
+}
 
 struct SortStats {
   int32_t count[kNumCls];
@@ -137,8 +150,10 @@ constexpr int kClassTile = 4096;
 
 __device__ __forceinline__ int seg_class(int64_t len) {
   if (len <= 0) return -1;
-  return len <= 1 ? kClsCopy : len <= kWave ? kClsWave : len <= kSmallTile ? kClsSmall
-         : len <= kBigTile ? kClsMid : kClsBig;
+  if (len > kBigTile) return kClsBig;
+  int c = kClsCopy;
+  while (class_cap(c) < len) ++c;
+  return c;
 }
 
 __global__ __launch_bounds__(256) void k_classify(const int64_t *seg_off, int64_t nseg,
@@ -181,15 +196,19 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t *seg_off, int64_
       int64_t len = 0;
       if (i < t1) len = seg_off[i + 1] - seg_off[i];
       const int c = i < t1 ? seg_class(len) : -1;
-      for (int k = 0; k < kNumCls; ++k) {
-        const uint64_t m = __ballot(c == k);
-        if (!m) continue;
+      // One round per class present in the wavefront (the class of the
+      // lowest pending lane, made uniform by readlane).
+      bool pending = c >= 0;
+      for (uint64_t act = __ballot(pending); act; act = __ballot(pending)) {
+        const int k = __builtin_amdgcn_readlane(c, __ffsll((unsigned long long)act) - 1);
+        const uint64_t m = __ballot(pending && c == k);
         const int leader = __ffsll((unsigned long long)m) - 1;
         const int32_t b = __builtin_amdgcn_readlane(atomicAdd(&cur[k], lane == leader ? __popcll(m) : 0), leader);
-        if (c == k) {
+        if (pending && c == k) {
           const int32_t pos = base[k] + b + __popcll(m & below);
           lists[k * cap + pos] = (int32_t)i;
           if (k == kClsBig) big_tiles_of[pos] = (int32_t)((len + kBigTile - 1) / kBigTile);
+          pending = false;
         }
       }
     }
@@ -216,16 +235,19 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Bitonic sort of one (key, id) per lane across the 64 lanes, ascending.
-__device__ __forceinline__ void wave_bitonic(uint64_t &k, int32_t &id, int lane) {
+// Bitonic sort of one (key, id) per lane within groups of S lanes, ascending
+// (pos = lane within the group; every exchange stride is below S, so it stays
+// inside the group).
+template <int S>
+__device__ __forceinline__ void group_bitonic(uint64_t &k, int32_t &id, int pos) {
 #pragma unroll
-  for (int size = 2; size <= kWave; size <<= 1) {
+  for (int size = 2; size <= S; size <<= 1) {
 #pragma unroll
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       uint64_t ok = shfl_xor_u64(k, stride);
       int32_t oid = __shfl_xor(id, stride, kWave);
-      bool asc = (lane & size) == 0;
-      bool lower = (lane & stride) == 0;
+      bool asc = (pos & size) == 0;
+      bool lower = (pos & stride) == 0;
       bool other_less = key_less(ok, oid, k, id);
       bool take = (lower == asc) ? other_less : key_less(k, id, ok, oid);
       if (take) {
@@ -236,27 +258,35 @@ __device__ __forceinline__ void wave_bitonic(uint64_t &k, int32_t &id, int lane)
   }
 }
 
-__global__ __launch_bounds__(256) void k_sort_wave(const int64_t *seg_off, const int32_t *list,
-                                                   const int32_t *countp, const double *kin,
-                                                   const int32_t *iin, double *kout,
-                                                   int32_t *iout) {
+// Segments of at most S elements; a wavefront sorts kWave / S of them, one
+// per group of S lanes.
+template <int S>
+__global__ __launch_bounds__(256) void k_sort_group(const int64_t *seg_off, const int32_t *list,
+                                                    const int32_t *countp, const double *kin,
+                                                    const int32_t *iin, double *kout, int32_t *iout) {
+  constexpr int G = kWave / S;
   const int32_t count = *countp;
-  int lane = threadIdx.x & (kWave - 1);
-  int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-  int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (; w < count; w += nw) {
-    int64_t o = seg_off[list[w]];
-    int len = (int)(seg_off[list[w] + 1] - o);
+  const int lane = threadIdx.x & (kWave - 1), grp = lane / S, pos = lane % S;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; w * G < count; w += nw) {
+    const int64_t idx = w * G + grp;
+    int64_t o = 0;
+    int len = 0;
+    if (idx < count) {
+      const int32_t sg = list[idx];
+      o = seg_off[sg];
+      len = (int)(seg_off[sg + 1] - o);
+    }
     uint64_t k = kPadKey;
     int32_t id = kPadId;
-    if (lane < len) {
-      k = desc_key(kin[o + lane]);
-      id = iin[o + lane];
+    if (pos < len) {
+      k = desc_key(kin[o + pos]);
+      id = iin[o + pos];
     }
-    wave_bitonic(k, id, lane);
-    if (lane < len) {
-      kout[o + lane] = key_to_sim(k);
-      iout[o + lane] = id;
+    group_bitonic<S>(k, id, pos);
+    if (pos < len) {
+      kout[o + pos] = key_to_sim(k);
+      iout[o + pos] = id;
     }
   }
 }
@@ -305,8 +335,8 @@ struct BlockSort {
 
   // Registers (blocked: thread t holds positions [t*ITEMS, (t+1)*ITEMS)) of
   // sorted runs of width ITEMS -> one sorted run of N, blocked.
-  __device__ static void merge_stages(Smem &s, uint64_t (&k)[ITEMS], int32_t (&id)[ITEMS]) {
-    const int o = threadIdx.x * ITEMS;
+  __device__ static void merge_stages(Smem &s, uint64_t (&k)[ITEMS], int32_t (&id)[ITEMS], int t) {
+    const int o = t * ITEMS;
 #pragma unroll 1
     for (int w = ITEMS; w < N; w <<= 1) {
 #pragma unroll
@@ -343,7 +373,11 @@ struct BlockSort {
   // for i < len. Starts and ends with all threads past a barrier.
   template <class Load, class Store>
   __device__ static void run(Smem &s, int len, Load load, Store store) {
-    const int t = threadIdx.x;
+    // The thread index passes through an empty asm statement, so the
+    // per-element addresses derived from it are computed per call: hoisted
+    // out of a caller's loop they occupy over a hundred registers.
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
 #pragma unroll
     for (int x = 0; x < ITEMS; ++x) {
       const int i = x * THREADS + t;
@@ -363,7 +397,7 @@ struct BlockSort {
     }
     __syncthreads();
     thread_sort(k, id);
-    merge_stages(s, k, id);
+    merge_stages(s, k, id, t);
 #pragma unroll
     for (int x = 0; x < ITEMS; ++x) {
       s.K[lds_pad(t * ITEMS + x)] = k[x];
@@ -608,15 +642,27 @@ scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
   if (h.count[kClsCopy])
     k_sort_copy<<<grid_for(h.count[kClsCopy], 256), 256, 0, s>>>(seg_off, lists + kClsCopy * nseg, cnt + kClsCopy,
                                                                  key_in, id_in, key_out, id_out);
-  if (h.count[kClsWave])
-    k_sort_wave<<<grid_for((int64_t)h.count[kClsWave] * kWave, 256), 256, 0, s>>>(
-        seg_off, lists + kClsWave * nseg, cnt + kClsWave, key_in, id_in, key_out, id_out);
-  if (h.count[kClsSmall])
-    k_sort_block<64, kSmallTile / 64><<<grid_for(h.count[kClsSmall], 1), 64, 0, s>>>(
-        seg_off, lists + kClsSmall * nseg, cnt + kClsSmall, key_in, id_in, key_out, id_out);
-  if (h.count[kClsMid])
-    k_sort_block<kSortBlock, kBigTile / kSortBlock><<<grid_for(h.count[kClsMid], 1), kSortBlock, 0, s>>>(
-        seg_off, lists + kClsMid * nseg, cnt + kClsMid, key_in, id_in, key_out, id_out);
+#define SCAN_GROUP(S, C)                                                                      \
+  if (h.count[C])                                                                              \
+    k_sort_group<S><<<grid_for(((int64_t)h.count[C] + kWave / (S) - 1) / (kWave / (S)) * kWave, 256), 256, 0, \
+                      s>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, id_in, key_out, id_out);
+  SCAN_GROUP(8, kClsW8)
+  SCAN_GROUP(16, kClsW16)
+  SCAN_GROUP(32, kClsW32)
+  SCAN_GROUP(64, kClsW64)
+#undef SCAN_GROUP
+#define SCAN_BLOCK(T, I, C)                                                                    \
+  static_assert((T) * (I) == class_cap(C), "block sort shape must match its class");          \
+  if (h.count[C])                                                                              \
+    k_sort_block<T, I><<<grid_for(h.count[C], 1), T, 0, s>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, \
+                                                             id_in, key_out, id_out);
+  SCAN_BLOCK(64, 2, kClsB128)
+  SCAN_BLOCK(64, 4, kClsB256)
+  SCAN_BLOCK(64, 8, kClsB512)
+  SCAN_BLOCK(128, 8, kClsB1024)
+  SCAN_BLOCK(256, 8, kClsB2048)
+  SCAN_BLOCK(kSortBlock, kBigTile / kSortBlock, kClsB4096)
+#undef SCAN_BLOCK
   if (h.count[kClsBig]) {
     const int32_t nbig = h.count[kClsBig];
     const int64_t ntiles = h.big_tiles;

@@ -1,7 +1,7 @@
 """The segmented sort behind the neighbour and core orders, through its
 diagnostic entry point: every segment sorted by key descending, ties by id
 ascending, for segment lengths across every size class of the sort (single
-elements, one wavefront, one block, one tile, several tiles merged in 1..5
+elements, lane groups of 8..64, blocks of 128..4096, several tiles merged in 1..5
 passes, with segments of different pass counts in one call), with many tied
 keys. Expected order: numpy's lexsort."""
 
@@ -15,7 +15,9 @@ from gpu_util import bits
 
 pytestmark = pytest.mark.gpu
 
-EDGE_LENGTHS = [0, 1, 2, 3, 63, 64, 65, 100, 511, 512, 513, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
+# Both sides of every class boundary (1, 8, 16, 32, 64, 128, ..., 4096).
+EDGE_LENGTHS = [0, 1, 2, 3, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257,
+                511, 512, 513, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
                 12289, 16384, 16385, 18859, 18859, 18859, 33000, 70001, 131072]
 
 
