@@ -62,11 +62,10 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
   return v;
 }
 
-// Sum and maximum over the wavefront with DPP row shifts and row broadcasts
+// Sum over the wavefront with DPP row shifts and row broadcasts
 // (register-path lane exchanges, no LDS crossbar): after row_shr 1, 2, 4, 8
 // each row's last lane holds the row total, row_bcast 15 and 31 carry the
 // totals to lane 63, which is read into a scalar. All lanes must be active.
-// For the maximum, lanes with no source read 0, so values must be >= 0.
 __device__ __forceinline__ int32_t dpp_wave_sum(int32_t v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
   v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
@@ -74,15 +73,6 @@ __device__ __forceinline__ int32_t dpp_wave_sum(int32_t v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
   v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true);  // row_bcast:15 into rows 1, 3
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true);  // row_bcast:31 into rows 2, 3
-  return __builtin_amdgcn_readlane(v, kWave - 1);
-}
-__device__ __forceinline__ int32_t dpp_wave_max_nonneg(int32_t v) {
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true));
   return __builtin_amdgcn_readlane(v, kWave - 1);
 }
 
@@ -328,7 +318,17 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
 constexpr int kBigThreads = 1024;
 constexpr int kUnroll = 4;   // loads in flight per lane
 constexpr int kSeg = 1024;   // ids per work item (rows longer than this are split)
-constexpr int kRest = kSeg / kWave - kUnroll;  // loads per lane for the rest of a long item
+constexpr int kItemLoads = kSeg / kWave;           // loads per lane per item
+constexpr int kGroups = kSeg / (kWave * kUnroll);  // probe groups per item
+
+// Word of the owner bitmap holding bit y. The bitmap starts the kernel's
+// dynamic LDS, which starts at LDS address 0 because the kernel has no
+// static LDS (the host checks), so the byte address is (y / 32) * 4: two
+// instructions, where a pointer to the bitmap costs a third (adding a base
+// the compiler cannot fold).
+__device__ __forceinline__ uint32_t bitmap_word(uint32_t y) {
+  return *(const __attribute__((address_space(3))) uint32_t *)(size_t)((y >> 3) & ~3u);
+}
 
 struct BigShared {
   int32_t chunk;
@@ -370,20 +370,21 @@ __device__ __forceinline__ int64_t wave_lower_bound(const int32_t *row, int64_t 
 template <bool kOneWindow>
 __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     const BigChunk *chunks, PlanCounts *pc, int spc, int wbits, int64_t n,
-    const int64_t *off, const int32_t *deg, const int32_t *adj, int kind, double *sims,
-    int32_t *counts) {
+    const int64_t *off, const int32_t *deg, const int32_t *adj, int64_t nnz, const int32_t *tail,
+    int64_t tail0, int kind, double *sims, int32_t *counts) {
   extern __shared__ unsigned char smem[];
   const int64_t W = (int64_t)1 << wbits;
   const int nwords = (int)(W >> 5);
   uint32_t *bm = (uint32_t *)smem;
   int64_t *le_ou = (int64_t *)(bm + nwords);
-  int64_t *le_mir = le_ou + spc;
-  int32_t *le_e = (int32_t *)(le_mir + spc);
+  int32_t *le_lt = (int32_t *)(le_ou + spc);  // ids below h in the row (one window)
+  int32_t *le_e = le_lt + spc;
   int32_t *le_du = le_e + spc;
   int32_t *le_cnt = le_du + spc;
   int32_t *le_b0 = le_cnt + spc;
   int32_t *le_b1 = le_b0 + spc;  // end of the range in the current window (cursor)
-  int32_t *le_xp = le_b1 + spc;  // [spc + 1] exclusive prefix of extra segments
+  int32_t *le_lim = le_b1 + spc;  // largest item start whose kSeg ids lie inside adj
+  int32_t *le_xp = le_lim + spc;  // [spc + 1] exclusive prefix of extra segments
   BigShared *sh = (BigShared *)(le_xp + spc + 1);
   const int tid = threadIdx.x, lane = lane_id();
   constexpr bool one_window = kOneWindow;  // the whole id space fits one window
@@ -427,7 +428,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         le_du[k] = du;
         le_ou[k] = off[u];
         le_cnt[k] = 0;
-        le_mir[k] = -1;
+        le_lt[k] = 0;
+        le_lim[k] = (int32_t)max((int64_t)-1, min((int64_t)INT32_MAX, nnz - kSeg - off[u]));
         le_b0[k] = 0;
         le_b1[k] = one_window ? du : 0;
       }
@@ -474,12 +476,16 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       // Software pipeline over work items: the next item is claimed and its
       // first kWave*kUnroll ids are requested before the current item's ids
       // are probed, so two items' loads are in flight per wavefront.
-      auto claim = [&](int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou) {
-        const int32_t j = uniform(atomicAdd(&sh->next, lane == 0 ? 1 : 0));
+      // Every lane adds 1 (a uniform operand, which the compiler folds into
+      // one atomic of the active-lane count), so a claim advances the
+      // counter by kWave and the item index is the old value / kWave.
+      auto claim = [&](int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou, int32_t &lim) {
+        const int32_t j = uniform(atomicAdd(&sh->next, 1)) / kWave;
         if (j >= nitems) {
           e = -1;
           lo = hi = 0;
           ou = 0;
+          lim = INT32_MAX;
           return;
         }
         int32_t ee = j, sg = 0;
@@ -496,108 +502,86 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         }
         e = ee;
         ou = uniform64(le_ou[ee]);
+        lim = uniform(le_lim[ee]);
         lo = uniform(le_b0[ee]) + sg * kSeg;
         hi = min(uniform(le_b1[ee]), lo + kSeg);
       };
-      // Branch-free loads (a lane past the end reads adj[0] and discards it)
-      // keep the loads unconditional, so the compiler waits only for the ones
-      // it consumes.
-      // Loads are branch-free (a lane past the end re-reads the row's first
-      // id and discards it) and their values are only read by the probe, so
-      // the compiler waits only for the loads it consumes. Hits and the
-      // position of h are kept per lane and reduced once per item.
-      // Validity is applied with masks, not branches (mask = all ones for a
-      // lane inside the item, zero past its end).
-      auto fetch = [&](int32_t x[kUnroll], const int32_t *row, uint32_t base, uint32_t hi) {
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-          const uint32_t q = base + k * kWave + lane;
-          const uint32_t vm = 0u - (uint32_t)(q < hi);
-          x[k] = row[q & vm];
-        }
+      // Ids [lo, lo + kSeg) of an item's row are readable through a uniform
+      // pointer: into adj, or, within kSeg ids of its end, into `tail`, a
+      // zero-padded copy of adj[tail0, nnz). Loads are then unmasked and
+      // address the row as scalar base + lane offset + immediate; ids past
+      // the item's end are masked in the probe. The choice is a 32-bit
+      // compare with the edge's limit (le_lim), i.e. scalar code.
+      auto item_ptr = [&](int64_t ou, int32_t lo, int32_t lim) -> const int32_t * {
+        return lo <= lim ? adj + ou + lo : tail + (ou + lo - tail0);
       };
-      // The same for the rest of a long item, all of whose loads are issued
-      // before any is used.
-      auto fetch_rest = [&](int32_t x[kRest], const int32_t *row, uint32_t base, uint32_t hi) {
+      auto fetch = [&](int32_t x[kUnroll], const int32_t *rp) {
 #pragma unroll
-        for (int k = 0; k < kRest; ++k) {
-          const uint32_t q = base + k * kWave + lane;
-          const uint32_t vm = 0u - (uint32_t)(q < hi);
-          x[k] = row[q & vm];
-        }
+        for (int k = 0; k < kUnroll; ++k) x[k] = rp[k * kWave + lane];
       };
-      auto probe = [&](const int32_t x[kUnroll], uint32_t base, uint32_t hi, int32_t &cnt,
-                       int32_t &mpi) {
+      // Probes the group of kWave * kUnroll ids that starts at position g0
+      // of an item of len ids. Per lane, acc counts the hits (low half) and
+      // the ids below h (high half): rows are sorted, so with one window the
+      // position of h in the lower neighbour's row is the sum of the latter
+      // over the row's items. Both halves stay below 2^16 (<= kSeg per item).
+      auto probe_group = [&](const int32_t x[kUnroll], int32_t g0, int32_t len, uint32_t &acc) {
+        if (g0 + kWave * kUnroll <= len) {
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-          const uint32_t q = base + k * kWave + lane;
-          const uint32_t vb = (uint32_t)(q < hi);
-          const uint32_t vm = 0u - vb;
-          // inside [lo, hi) every id lies in the current window
-          const uint32_t y = kOneWindow ? (uint32_t)x[k] : (uint32_t)(x[k] - (int32_t)w0);
-          const uint32_t word = bm[(y >> 5) & vm];
-          cnt += (int32_t)((word >> (y & 31u)) & vb);
-          const uint32_t eq = (uint32_t)(x[k] == h) & vb;
-          mpi = eq ? (int32_t)q : mpi;
-        }
-      };
-      // A chunk with all kWave * kUnroll ids inside the item needs no masks
-      // (the branch between the two holds no loads).
-      auto probe_full = [&](const int32_t x[kUnroll], uint32_t base, int32_t &cnt, int32_t &mpi) {
+          for (int k = 0; k < kUnroll; ++k) {
+            const uint32_t y = kOneWindow ? (uint32_t)x[k] : (uint32_t)(x[k] - (int32_t)w0);
+            acc += __builtin_amdgcn_ubfe(bitmap_word(y), y, 1) + (x[k] < h ? 0x10000u : 0u);  // bit y & 31
+          }
+        } else {
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-          const uint32_t y = kOneWindow ? (uint32_t)x[k] : (uint32_t)(x[k] - (int32_t)w0);
-          cnt += (int32_t)((bm[y >> 5] >> (y & 31u)) & 1u);
-          mpi = x[k] == h ? (int32_t)(base + k * kWave + lane) : mpi;
-        }
-      };
-      auto probe_any = [&](const int32_t x[kUnroll], uint32_t base, uint32_t hi, int32_t &cnt, int32_t &mpi) {
-        if (base + kWave * kUnroll <= hi) probe_full(x, base, cnt, mpi);
-        else probe(x, base, hi, cnt, mpi);
-      };
-      int32_t ea, loa, hia;
-      int64_t oua;
-      int32_t xa[kUnroll];
-      claim(ea, loa, hia, oua);
-      fetch(xa, adj + oua, (uint32_t)loa, (uint32_t)hia);
-      while (ea >= 0) {
-        int32_t eb, lob, hib;
-        int64_t oub;
-        int32_t xb[kUnroll];
-        claim(eb, lob, hib, oub);
-        fetch(xb, adj + oub, (uint32_t)lob, (uint32_t)hib);
-        int32_t cnt = 0, mpi = -1;
-        probe_any(xa, (uint32_t)loa, (uint32_t)hia, cnt, mpi);
-        // The rest of the item (at most kSeg - kWave * kUnroll ids): one chunk
-        // if it fits, else all of it at once, so it costs one load latency.
-        const uint32_t r0 = (uint32_t)loa + kWave * kUnroll;
-        if (r0 < (uint32_t)hia) {
-          if ((uint32_t)hia - r0 <= kWave * kUnroll) {
-            int32_t x[kUnroll];
-            fetch(x, adj + oua, r0, (uint32_t)hia);
-            probe_any(x, r0, (uint32_t)hia, cnt, mpi);
-          } else {
-            int32_t x[kRest];
-            fetch_rest(x, adj + oua, r0, (uint32_t)hia);
-#pragma unroll
-            for (int c = 0; c < kRest / kUnroll; ++c)
-              probe_any(x + c * kUnroll, r0 + c * kWave * kUnroll, (uint32_t)hia, cnt, mpi);
+          for (int k = 0; k < kUnroll; ++k) {
+            const bool valid = g0 + k * kWave + lane < len;
+            const uint32_t vm = 0u - (uint32_t)valid;
+            // inside the item every id lies in the current window
+            const uint32_t y = kOneWindow ? (uint32_t)x[k] : (uint32_t)(x[k] - (int32_t)w0);
+            acc += (__builtin_amdgcn_ubfe(bitmap_word(y & vm), y, 1) + (x[k] < h ? 0x10000u : 0u)) & vm;
           }
         }
-        const int32_t t = dpp_wave_sum(cnt);
-        const int32_t mp = dpp_wave_max_nonneg(mpi + 1) - 1;
-        // t and mp are wave-uniform scalars: lane 0 records them (no return
-        // value is used, so no lane waits on another).
-        if (lane == 0) {
-          atomicAdd(&le_cnt[ea], t);
-          if (mp >= 0) le_mir[ea] = oua + mp;
-        }
-        ea = eb;
-        loa = lob;
-        hia = hib;
-        oua = oub;
+      };
+      // Whole items are requested one item ahead, and the loop body is
+      // unrolled twice so the two register sets swap roles without register
+      // copies (a copy waits for its load). Every group of an item is
+      // loaded: a fixed count keeps the waits exact (the compiler waits for
+      // an item's loads by counting the loads issued after them); a group
+      // past the item's end re-reads the first group's ids, which are
+      // cached, instead of fetching new lines, and is not probed.
+      auto fetch_item = [&](int32_t x[kItemLoads], const int32_t *rp, int32_t len) {
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) xa[k] = xb[k];
+        for (int c = 0; c < kGroups; ++c) fetch(x + c * kUnroll, len > c * kWave * kUnroll ? rp + c * kWave * kUnroll : rp);
+      };
+      auto probe_item = [&](const int32_t x[kItemLoads], int32_t e, int32_t len) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int c = 0; c < kGroups; ++c)
+          if (c == 0 || len > c * kWave * kUnroll) probe_group(x + c * kUnroll, c * kWave * kUnroll, len, acc);
+        const uint32_t t = (uint32_t)dpp_wave_sum((int32_t)acc);
+        // t is wave-uniform: lane 0 records it (no return value is used, so
+        // no lane waits on another)
+        if (lane == 0) {
+          atomicAdd(&le_cnt[e], (int32_t)(t & 0xffffu));
+          if (kOneWindow) atomicAdd(&le_lt[e], (int32_t)(t >> 16));
+        }
+      };
+      // Items are claimed one step further ahead, after a probe has freed
+      // its registers, so no claim waits on loads in flight.
+      int32_t ea, loa, hia, lima, eb, lob, hib, limb;
+      int64_t oua, oub;
+      int32_t xa[kItemLoads], xb[kItemLoads];
+      claim(ea, loa, hia, oua, lima);
+      fetch_item(xa, item_ptr(oua, loa, lima), hia - loa);
+      claim(eb, lob, hib, oub, limb);
+      while (ea >= 0) {
+        fetch_item(xb, item_ptr(oub, lob, limb), hib - lob);
+        probe_item(xa, ea, hia - loa);
+        claim(ea, loa, hia, oua, lima);
+        if (eb < 0) break;
+        fetch_item(xa, item_ptr(oua, loa, lima), hia - loa);
+        probe_item(xb, eb, hib - lob);
+        claim(eb, lob, hib, oub, limb);
       }
       __syncthreads();
       for (int64_t i = p + tid; i < pe; i += blockDim.x) {
@@ -610,8 +594,12 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     }
     __syncthreads();
     for (int i = tid; i < nlow; i += blockDim.x) {
-      int64_t mir = le_mir[i];
-      if (!one_window) {
+      int64_t mir = -1;
+      if (one_window) {
+        // h sits after the ids below it (absent only from an asymmetric row)
+        const int32_t lt = le_lt[i];
+        if (lt < le_du[i] && adj[le_ou[i] + lt] == h) mir = le_ou[i] + lt;
+      } else {
         // h may lie in a window that holds no id of N(h): locate it directly
         const int64_t ou = le_ou[i];
         int64_t lo = 0, hi = le_du[i];
@@ -631,7 +619,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
 // Host side.
 
 static size_t big_lds_bytes(int wbits, int spc) {
-  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 8 + 4 * 6) + 4 + sizeof(BigShared);
+  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 4 * 8) + 4 + sizeof(BigShared);
 }
 
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
@@ -698,19 +686,29 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   }
   if (stats && stats->ev_mid) (void)hipEventRecord(stats->ev_mid, s);
   if (h.big) {
+    // the last kSeg ids of adj, zero-padded to 2 * kSeg (see k_big_owner)
+    const int64_t tail0 = nnz > kSeg ? nnz - kSeg : 0;
+    int32_t *tail;
+    SCAN_TRY(tmp.alloc(&tail, 2 * kSeg));
+    SCAN_HIP_TRY(hipMemsetAsync(tail, 0, 2 * kSeg * sizeof(int32_t), s));
+    SCAN_HIP_TRY(hipMemcpyAsync(tail, adj + tail0, (nnz - tail0) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     size_t lds = big_lds_bytes(wbits, cfg.spc);
     const bool one = n <= ((int64_t)1 << wbits);
     const void *fn = one ? (const void *)k_big_owner<true> : (const void *)k_big_owner<false>;
+    hipFuncAttributes fa;
+    SCAN_HIP_TRY(hipFuncGetAttributes(&fa, fn));
+    if (fa.sharedSizeBytes != 0)  // bitmap_word assumes the dynamic LDS starts at address 0
+      return fail(SCAN_EDEVICE, "k_big_owner has %zu bytes of static LDS", (size_t)fa.sharedSizeBytes);
     if (lds > 65536)
       SCAN_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (size_t)lds_max / lds));
     const int grid = (int)std::min<int64_t>((int64_t)cus * per_cu, h.big);
     if (one)
-      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj,
-                                                       kind, sims, counts);
+      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nnz,
+                                                       tail, tail0, kind, sims, counts);
     else
-      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj,
-                                                        kind, sims, counts);
+      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nnz,
+                                                        tail, tail0, kind, sims, counts);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);

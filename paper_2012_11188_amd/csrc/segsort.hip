@@ -504,72 +504,126 @@ __device__ __forceinline__ int64_t wave_co_rank(const uint64_t *KA, const int32_
   return lo;
 }
 
+// Where the merge of pass q places a big tile's pair: the pass-i run pair
+// containing tile t of segment b (see k_big_merge for i and the runs).
+struct MergePair {
+  int i;            // the segment's own pass number (< 1: no pass now)
+  bool last;        // its final pass
+  int64_t o, len;   // segment
+  int64_t a0, la, b0, lb, ostart;  // runs A = [a0, a0+la), B = [b0, b0+lb); tile's first output
+  int cnt;          // outputs of the tile
+};
+__device__ __forceinline__ MergePair merge_pair(const int64_t *seg_off, const int32_t *big_list,
+                                                const int32_t *tile_seg, const int64_t *tile_first,
+                                                int64_t t, int q, int max_passes) {
+  MergePair m;
+  const int32_t b = tile_seg[t];
+  const int64_t seg = big_list[b];
+  m.o = seg_off[seg];
+  m.len = seg_off[seg + 1] - m.o;
+  const int P = passes_for(m.len);
+  m.i = q - (max_passes - P);
+  m.last = m.i == P;
+  const int64_t w = (int64_t)kBigTile << (m.i >= 1 ? m.i - 1 : 0);
+  const int64_t tstart = (t - tile_first[b]) * kBigTile;
+  m.a0 = tstart / (2 * w) * 2 * w;
+  m.la = min(w, m.len - m.a0);
+  m.b0 = m.a0 + m.la;
+  m.lb = max((int64_t)0, min(w, m.len - m.b0));
+  m.ostart = tstart - m.a0;
+  m.cnt = (int)min((int64_t)kBigTile, m.len - tstart);
+  return m;
+}
+
+// Merge splits of pass q: split[t] = elements of run A among the outputs of
+// its pair that precede tile t's first output. One wavefront per tile, so
+// the dependent searches of all tiles run concurrently, ahead of the merge.
+__global__ __launch_bounds__(256) void k_big_split(const int64_t *seg_off, const int32_t *big_list,
+                                                   const int32_t *tile_seg, const int64_t *tile_first,
+                                                   const int32_t *ntilesp, int q, const int32_t *max_passesp,
+                                                   const uint64_t *KA, const int32_t *IA, const uint64_t *KB,
+                                                   const int32_t *IB, int64_t *split) {
+  const int max_passes = *max_passesp;
+  if (q > max_passes) return;
+  const int64_t ntiles = *ntilesp;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; t < ntiles; t += nw) {
+    const MergePair m = merge_pair(seg_off, big_list, tile_seg, tile_first, t, q, max_passes);
+    if (m.i < 1) continue;  // uniform across the wavefront
+    const uint64_t *sK = (m.i & 1) ? KA : KB;
+    const int32_t *sI = (m.i & 1) ? IA : IB;
+    const int64_t r = wave_co_rank(sK + m.o + m.a0, sI + m.o + m.a0, m.la, sK + m.o + m.b0, sI + m.o + m.b0,
+                                   m.lb, m.ostart);
+    if ((threadIdx.x & (kWave - 1)) == 0) split[t] = r;
+  }
+}
+
 // One merge-path pass for all big segments. Global pass q (1-based) of
 // max_passes; a segment needing P passes does its pass i = q - (max_passes -
 // P) when i >= 1, merging runs of width kBigTile << (i-1). Pass i reads A if
 // i is odd, else B; writes B / A, or the final output when i == P.
 __global__ __launch_bounds__(kSortBlock) void k_big_merge(
     const int64_t *seg_off, const int32_t *big_list, const int32_t *tile_seg,
-    const int64_t *tile_first, const int32_t *ntilesp, int q, const int32_t *max_passesp, uint64_t *KA,
-    int32_t *IA, uint64_t *KB, int32_t *IB, double *kout, int32_t *iout) {
+    const int64_t *tile_first, const int32_t *ntilesp, int q, const int32_t *max_passesp,
+    const int64_t *split, uint64_t *KA, int32_t *IA, uint64_t *KB, int32_t *IB, double *kout,
+    int32_t *iout) {
   const int max_passes = *max_passesp;
   if (q > max_passes) return;  // launched against an upper bound on the passes
   const int64_t ntiles = *ntilesp;
   __shared__ uint64_t K[kBigTile + kBigTile / 16];  // padded indices (lds_pad)
   __shared__ int32_t I[kBigTile + kBigTile / 16];
-  __shared__ int64_t bounds[4];
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int32_t b = tile_seg[t];
-    int64_t seg = big_list[b];
-    int64_t o = seg_off[seg];
-    int64_t len = seg_off[seg + 1] - o;
-    int P = passes_for(len);
-    int i = q - (max_passes - P);
-    if (i < 1) continue;  // uniform across the block
-    const uint64_t *sK = (i & 1) ? KA : KB;
-    const int32_t *sI = (i & 1) ? IA : IB;
-    uint64_t *dK = (i & 1) ? KB : KA;
-    int32_t *dI = (i & 1) ? IB : IA;
-    bool last = (i == P);
-    int64_t w = (int64_t)kBigTile << (i - 1);
-    int64_t tstart = (t - tile_first[b]) * kBigTile;
-    int64_t pair = tstart / (2 * w);
-    int64_t a0 = pair * 2 * w;
-    int64_t la = min(w, len - a0);
-    int64_t b0 = a0 + la;
-    int64_t lb = max((int64_t)0, min(w, len - b0));
-    const uint64_t *AK = sK + o + a0;
-    const int32_t *AI = sI + o + a0;
-    const uint64_t *BK = sK + o + b0;
-    const int32_t *BI = sI + o + b0;
-    int64_t ostart = tstart - a0;
-    int cnt = (int)min((int64_t)kBigTile, len - tstart);
-    __syncthreads();
-    const int wave = threadIdx.x / kWave;
-    if (wave < 2) {  // wave 0: where this tile's outputs start, wave 1: end
-      const int64_t oo = wave == 0 ? ostart : ostart + cnt;
-      const int64_t r = wave_co_rank(AK, AI, la, BK, BI, lb, oo);
-      if ((threadIdx.x & (kWave - 1)) == 0) {
-        bounds[wave] = r;
-        bounds[2 + wave] = oo - r;
+    const MergePair m = merge_pair(seg_off, big_list, tile_seg, tile_first, t, q, max_passes);
+    if (m.i < 1) continue;  // uniform across the block
+    int tid = threadIdx.x;  // opaque per tile: keeps per-element addresses out of registers
+    asm volatile("" : "+v"(tid));
+    const int64_t o = m.o, tstart = m.a0 + m.ostart;
+    const int cnt = m.cnt;
+    const bool last = m.last;
+    const uint64_t *sK = (m.i & 1) ? KA : KB;
+    const int32_t *sI = (m.i & 1) ? IA : IB;
+    uint64_t *dK = (m.i & 1) ? KB : KA;
+    int32_t *dI = (m.i & 1) ? IB : IA;
+    const uint64_t *AK = sK + o + m.a0;
+    const int32_t *AI = sI + o + m.a0;
+    const uint64_t *BK = sK + o + m.b0;
+    const int32_t *BI = sI + o + m.b0;
+    // The tile's outputs take A[i0, i1) and B[j0, j1); the next tile of the
+    // pair starts where this one ends.
+    const int64_t i0 = split[t];
+    const int64_t i1 = m.ostart + cnt == m.la + m.lb ? m.la : split[t + 1];
+    const int64_t j0 = m.ostart - i0, j1 = m.ostart + cnt - i1;
+    const int na = (int)(i1 - i0), nb = (int)(j1 - j0);
+    __syncthreads();  // the previous tile's readers of K / I are done
+    // Stage A[i0, i1) at K[0, na) and B[j0, j1) at K[na, na + nb): all of a
+    // thread's loads are issued before its first LDS store.
+    {
+      uint64_t sk[kMergeItems];
+      int32_t si[kMergeItems];
+#pragma unroll
+      for (int x = 0; x < kMergeItems; ++x) {
+        const int e = x * kSortBlock + tid;
+        if (e < cnt) {
+          const bool in_a = e < na;
+          const uint64_t *pk = in_a ? AK + i0 + e : BK + j0 + (e - na);
+          const int32_t *pi = in_a ? AI + i0 + e : BI + j0 + (e - na);
+          sk[x] = *pk;
+          si[x] = *pi;
+        }
       }
-    }
-    __syncthreads();
-    int64_t i0 = bounds[0], i1 = bounds[1], j0 = bounds[2], j1 = bounds[3];
-    int na = (int)(i1 - i0), nb = (int)(j1 - j0);
-    // Stage A[i0, i1) at K[0, na) and B[j0, j1) at K[na, na + nb).
-    for (int x = threadIdx.x; x < na; x += blockDim.x) {
-      K[lds_pad(x)] = AK[i0 + x];
-      I[lds_pad(x)] = AI[i0 + x];
-    }
-    for (int x = threadIdx.x; x < nb; x += blockDim.x) {
-      K[lds_pad(na + x)] = BK[j0 + x];
-      I[lds_pad(na + x)] = BI[j0 + x];
+#pragma unroll
+      for (int x = 0; x < kMergeItems; ++x) {
+        const int e = x * kSortBlock + tid;
+        if (e < cnt) {
+          K[lds_pad(e)] = sk[x];
+          I[lds_pad(e)] = si[x];
+        }
+      }
     }
     __syncthreads();
     uint64_t rk[kMergeItems];
     int32_t ri[kMergeItems];
-    int my0 = threadIdx.x * kMergeItems;
+    int my0 = tid * kMergeItems;
     if (my0 < cnt) {
       // merge-path split inside the staged tile
       int lo = my0 > nb ? my0 - nb : 0, hi = my0 < na ? my0 : na;
@@ -608,12 +662,12 @@ __global__ __launch_bounds__(kSortBlock) void k_big_merge(
     __syncthreads();
     int64_t gbase = o + tstart;
     if (last) {
-      for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+      for (int x = tid; x < cnt; x += kSortBlock) {
         kout[gbase + x] = key_to_sim(K[lds_pad(x)]);
         iout[gbase + x] = I[lds_pad(x)];
       }
     } else {
-      for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+      for (int x = tid; x < cnt; x += kSortBlock) {
         dK[gbase + x] = K[lds_pad(x)];
         dI[gbase + x] = I[lds_pad(x)];
       }
@@ -666,12 +720,13 @@ scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
   if (h.count[kClsBig]) {
     const int32_t nbig = h.count[kClsBig];
     const int64_t ntiles = h.big_tiles;
-    int64_t *tile_first, *scan_ws;
+    int64_t *tile_first, *scan_ws, *split;
     int32_t *tile_seg, *IA, *IB;
     uint64_t *KA, *KB;
     SCAN_TRY(arena.alloc(&tile_first, nbig + 1));
     SCAN_TRY(arena.alloc(&scan_ws, scan_workspace_elems(nbig)));
     SCAN_TRY(arena.alloc(&tile_seg, ntiles));
+    SCAN_TRY(arena.alloc(&split, ntiles));
     SCAN_TRY(arena.alloc(&KA, total));
     SCAN_TRY(arena.alloc(&KB, total));
     SCAN_TRY(arena.alloc(&IA, total));
@@ -681,10 +736,14 @@ scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
     k_big_tiles<<<grid_for(nbig, 1, 4096), 256, 0, s>>>(big_tiles_of, tile_first, cnt + kClsBig, tile_seg);
     k_big_tile_sort<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
                                                                &st->big_tiles, key_in, id_in, KA, IA);
-    for (int q = 1; q <= h.max_passes; ++q)
+    for (int q = 1; q <= h.max_passes; ++q) {
+      k_big_split<<<grid_for(ntiles * kWave, 256), 256, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
+                                                                &st->big_tiles, q, &st->max_passes, KA, IA, KB,
+                                                                IB, split);
       k_big_merge<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
-                                                             &st->big_tiles, q, &st->max_passes, KA, IA, KB, IB,
-                                                             key_out, id_out);
+                                                             &st->big_tiles, q, &st->max_passes, split, KA, IA,
+                                                             KB, IB, key_out, id_out);
+    }
   }
   SCAN_HIP_TRY(hipGetLastError());
   return SCAN_OK;

@@ -82,3 +82,19 @@ def test_autotune(graphs):
     ix = scan.scan_build_index(*device_csr(g), scan.COSINE, FLAGS, tune=tune)
     torch.cuda.synchronize()
     assert_index_equal(ix, oix[scan.COSINE], g)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tune_tiny_bitmap_owners(seed):
+    """Graphs whose whole adjacency is shorter than one work item of the
+    bitmap owners (the rows near the end of the adjacency are read through
+    its padded tail copy), with every owner of degree >= 2 on that path."""
+    import torch
+
+    g = graphgen.random_graph(40 + 10 * seed, 0.2, seed=seed)
+    assert g.nnz < 1024
+    for kind in (scan.COSINE, scan.JACCARD):
+        oix = oracle.build_index(g, kind, threads=1)
+        ix = scan.scan_build_index(*device_csr(g), kind, FLAGS, tune={"small_max": 1, "spc": 4})
+        torch.cuda.synchronize()
+        assert_index_equal(ix, oix, g)
