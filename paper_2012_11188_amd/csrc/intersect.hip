@@ -490,12 +490,17 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         }
         int32_t ee = j, sg = 0;
         if (j >= nlow) {
+          // the last edge with le_xp[e] <= jj (le_xp is non-decreasing and
+          // le_xp[0] = 0): a 64-way search, every lane sampling one edge
           const int32_t jj = j - nlow;
-          int32_t a0 = 0, a1 = nlow;  // last edge with le_xp[e] <= jj
-          while (a1 - a0 > 1) {
-            const int32_t mid = (a0 + a1) >> 1;
-            if (uniform(le_xp[mid]) <= jj) a0 = mid;
-            else a1 = mid;
+          int32_t a0 = 0, na = nlow;
+          while (na > 1) {
+            const int32_t step = (na + kWave - 1) / kWave;
+            const int32_t q = a0 + lane * step;
+            const int32_t c = __popcll(__ballot(q < a0 + na && le_xp[q] <= jj));  // >= 1: lane 0
+            const int32_t nb = a0 + (c - 1) * step;
+            na = min(step, a0 + na - nb);
+            a0 = nb;
           }
           ee = a0;
           sg = 1 + jj - uniform(le_xp[a0]);
@@ -534,6 +539,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         } else {
 #pragma unroll
           for (int k = 0; k < kUnroll; ++k) {
+            if (g0 + k * kWave >= len) break;  // uniform
             const bool valid = g0 + k * kWave + lane < len;
             const uint32_t vm = 0u - (uint32_t)valid;
             // inside the item every id lies in the current window
