@@ -171,12 +171,18 @@ scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_k
  *   wbits      LDS bitmap window of 2^wbits vertex ids for larger owners
  *              (10..24; default 20); lowered to what LDS holds and to the id
  *              space; when the ids span several windows each chunk sweeps the
- *              windows that hold its owner's neighbours */
+ *              windows that hold its owner's neighbours
+ *   flags      0, or SCAN_TUNE_SEARCH_WINDOWS: with several windows, locate
+ *              each lower neighbour's ids per window by search inside the
+ *              chunk instead of reading them from a per-row window table
+ *              ((windows + 1) * n * 4 bytes, built once per build; the search
+ *              is used anyway where the table would exceed 4 GiB) */
+#define SCAN_TUNE_SEARCH_WINDOWS 1
 typedef struct {
   int32_t small_max;
   int32_t spc;
   int32_t wbits;
-  int32_t reserved;  /* must be 0 */
+  int32_t flags;
 } scan_tune;
 
 /* scan_build_index_batch with explicit intersection shapes (tune may be

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libscan.so")
 SCAN_OK, SCAN_EINVAL, SCAN_EGRAPH, SCAN_ENOMEM, SCAN_EDEVICE, SCAN_EBUSY = 0, -1, -2, -3, -4, -5
 COSINE, JACCARD = 0, 1
 SCAN_VALIDATE, SCAN_KEEP_SIMS, SCAN_KEEP_COUNTS, SCAN_PROFILE = 1, 2, 4, 8
+SCAN_TUNE_SEARCH_WINDOWS = 1
 (ARR_OFFSETS, ARR_NO_IDS, ARR_NO_SIM, ARR_CO_OFF, ARR_CO_IDS, ARR_CO_THR, ARR_SIMS,
  ARR_COUNTS) = range(8)
 _ARR_DTYPE = {ARR_OFFSETS: np.int64, ARR_NO_IDS: np.int32, ARR_NO_SIM: np.float64,
@@ -61,7 +62,7 @@ class _Profile(ctypes.Structure):
 
 class _Tune(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("spc", ctypes.c_int32), ("wbits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -266,13 +267,14 @@ def _csr_struct(off, adj):
 
 
 def _tune_struct(tune):
-    """dict (small_max / spc / wbits; missing or 0 = default) -> scan_tune, or None."""
+    """dict (small_max / spc / wbits / flags; missing or 0 = default) -> scan_tune, or None."""
     if tune is None:
         return None
-    unknown = set(tune) - {"small_max", "spc", "wbits"}
+    unknown = set(tune) - {"small_max", "spc", "wbits", "flags"}
     if unknown:
         raise ValueError(f"unknown tune fields {sorted(unknown)}")
-    return _Tune(int(tune.get("small_max", 0)), int(tune.get("spc", 0)), int(tune.get("wbits", 0)), 0)
+    return _Tune(int(tune.get("small_max", 0)), int(tune.get("spc", 0)), int(tune.get("wbits", 0)),
+                 int(tune.get("flags", 0)))
 
 
 def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None, tune=None) -> Index:

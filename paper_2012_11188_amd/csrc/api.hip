@@ -187,7 +187,8 @@ static scan_status query_impl(const scan_index *cix, int32_t count, const int32_
 static scan_status tune_to_config(const scan_tune *t, IntersectConfig *c) {
   *c = default_config();
   if (!t) return SCAN_OK;
-  if (t->reserved != 0) return fail(SCAN_EINVAL, "scan_tune.reserved must be 0");
+  if (t->flags & ~SCAN_TUNE_SEARCH_WINDOWS) return fail(SCAN_EINVAL, "unknown scan_tune.flags %d", t->flags);
+  c->search_windows = (t->flags & SCAN_TUNE_SEARCH_WINDOWS) != 0;
   if (t->small_max) c->small_max = t->small_max;
   if (t->spc) c->spc = t->spc;
   if (t->wbits) c->wbits = t->wbits;

@@ -15,6 +15,7 @@ struct IntersectConfig {
   int32_t small_max = 256;  // owners of degree <= small_max: one wavefront each
   int32_t spc = 512;        // row slots per chunk of a larger owner
   int32_t wbits = 20;       // LDS bitmap window of 2^wbits ids (clamped to LDS)
+  bool search_windows = false;  // several windows: search row ranges instead of tabling them
 };
 
 struct IntersectStats {

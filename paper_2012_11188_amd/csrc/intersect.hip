@@ -371,7 +371,7 @@ template <bool kOneWindow>
 __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     const BigChunk *chunks, PlanCounts *pc, int spc, int wbits, int64_t n,
     const int64_t *off, const int32_t *deg, const int32_t *adj, int64_t nnz, const int32_t *tail,
-    int64_t tail0, int kind, double *sims, int32_t *counts) {
+    int64_t tail0, const int32_t *wt, int32_t nwin, int kind, double *sims, int32_t *counts) {
   extern __shared__ unsigned char smem[];
   const int64_t W = (int64_t)1 << wbits;
   const int nwords = (int)(W >> 5);
@@ -384,7 +384,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
   int32_t *le_b0 = le_cnt + spc;
   int32_t *le_b1 = le_b0 + spc;  // end of the range in the current window (cursor)
   int32_t *le_lim = le_b1 + spc;  // largest item start whose kSeg ids lie inside adj
-  int32_t *le_xp = le_lim + spc;  // [spc + 1] exclusive prefix of extra segments
+  int32_t *le_u = le_lim + spc;   // the lower neighbour
+  int32_t *le_xp = le_u + spc;    // [spc + 1] exclusive prefix of extra segments
   BigShared *sh = (BigShared *)(le_xp + spc + 1);
   const int tid = threadIdx.x, lane = lane_id();
   constexpr bool one_window = kOneWindow;  // the whole id space fits one window
@@ -425,6 +426,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       if (low) {
         const int k = base + __popcll(mk & lanes_below());
         le_e[k] = e;
+        le_u[k] = u;
         le_du[k] = du;
         le_ou[k] = off[u];
         le_cnt[k] = 0;
@@ -441,12 +443,23 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     int64_t p = 0;
     while (p < dh) {
       const int64_t w0 = one_window ? 0 : ((int64_t)adj[oh + p] >> wbits) << wbits;
-      const int64_t pe = one_window ? dh : wave_lower_bound(adj + oh, p, dh, (int32_t)min(w0 + W, (int64_t)INT32_MAX));
+      const int64_t pe = one_window ? dh
+                         : wt ? (int64_t)wt[(int64_t)h * (nwin + 1) + (w0 >> wbits) + 1]
+                              : wave_lower_bound(adj + oh, p, dh, (int32_t)min(w0 + W, (int64_t)INT32_MAX));
       for (int64_t i = p + tid; i < pe; i += blockDim.x) {
         const int32_t x = (int32_t)(adj[oh + i] - w0);
         atomicOr(&bm[x >> 5], 1u << (x & 31));
       }
-      if (!one_window) {
+      if (!one_window && wt) {
+        // each lower neighbour's ids inside this window, from the table
+        const int64_t kw = w0 >> wbits;
+        for (int i = tid; i < nlow; i += blockDim.x) {
+          const int32_t *t = wt + (int64_t)le_u[i] * (nwin + 1) + kw;
+          le_b0[i] = t[0];
+          le_b1[i] = t[1];
+        }
+        __syncthreads();
+      } else if (!one_window) {
         // each lower neighbour's ids inside this window, after the last one
         if (tid == 0) sh->next = 0;
         __syncthreads();
@@ -621,11 +634,39 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
   }
 }
 
+// Window table of every row: wt[u * (nwin + 1) + k] = the first position in
+// row u whose id is >= k * 2^wbits (k = 0..nwin), so that a lower
+// neighbour's ids inside window k are positions [wt[k], wt[k + 1]) of its
+// row. One wavefront per row, 64 ids per step: a lane whose id opens
+// windows past its left neighbour's writes their starts (every entry is
+// written once); the step past the row's end closes the last windows.
+__global__ __launch_bounds__(256) void k_window_table(const int64_t *off, const int32_t *adj, int64_t n,
+                                                      int wbits, int32_t nwin, int32_t *wt) {
+  const int lane = lane_id();
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; u < n; u += nw) {
+    const int64_t o = off[u];
+    const int32_t d = (int32_t)(off[u + 1] - o);
+    int32_t *t = wt + u * (nwin + 1);
+    int32_t prev = -1;  // window of the id before this step (wave-uniform)
+    for (int32_t i0 = 0; i0 <= d; i0 += kWave) {
+      const int32_t i = i0 + lane;
+      const int32_t w = i < d ? adj[o + i] >> wbits : nwin;  // past the end: window nwin
+      int32_t wl = __shfl_up(w, 1, kWave);
+      if (lane == 0) wl = prev;
+      for (int32_t k = wl + 1; k <= w; ++k) t[k] = i;
+      prev = __shfl(w, kWave - 1, kWave);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
+constexpr size_t kMaxWindowTable = (size_t)4 << 30;
+
 static size_t big_lds_bytes(int wbits, int spc) {
-  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 4 * 8) + 4 + sizeof(BigShared);
+  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 4 * 9) + 4 + sizeof(BigShared);
 }
 
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
@@ -700,6 +741,15 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
     SCAN_HIP_TRY(hipMemcpyAsync(tail, adj + tail0, (nnz - tail0) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     size_t lds = big_lds_bytes(wbits, cfg.spc);
     const bool one = n <= ((int64_t)1 << wbits);
+    // Several windows: each row's window starts come from a table (one
+    // pass over adj) unless it would exceed kMaxWindowTable bytes or the
+    // searched ranges are asked for; then chunks search them per window.
+    int32_t *wt = nullptr;
+    const int32_t nwin = (int32_t)((n + ((int64_t)1 << wbits) - 1) >> wbits);
+    if (!one && !cfg.search_windows && (size_t)(nwin + 1) * (size_t)n * 4 <= kMaxWindowTable) {
+      SCAN_TRY(tmp.alloc(&wt, (int64_t)(nwin + 1) * n));
+      k_window_table<<<grid_for(n * kWave, 256), 256, 0, s>>>(off, adj, n, wbits, nwin, wt);
+    }
     const void *fn = one ? (const void *)k_big_owner<true> : (const void *)k_big_owner<false>;
     hipFuncAttributes fa;
     SCAN_HIP_TRY(hipFuncGetAttributes(&fa, fn));
@@ -711,10 +761,10 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
     const int grid = (int)std::min<int64_t>((int64_t)cus * per_cu, h.big);
     if (one)
       k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nnz,
-                                                       tail, tail0, kind, sims, counts);
+                                                       tail, tail0, nullptr, nwin, kind, sims, counts);
     else
       k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nnz,
-                                                        tail, tail0, kind, sims, counts);
+                                                        tail, tail0, wt, nwin, kind, sims, counts);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);

@@ -19,7 +19,8 @@ FLAGS = scan.SCAN_KEEP_SIMS | scan.SCAN_KEEP_COUNTS
 
 TUNES = [
     None,
-    {"wbits": 10},                              # several windows per chunk
+    {"wbits": 10},                              # several windows per chunk (tabled ranges)
+    {"wbits": 10, "flags": scan.SCAN_TUNE_SEARCH_WINDOWS},  # ... ranges searched per window
     {"wbits": 11, "spc": 1024},
     {"small_max": 1},                           # almost every owner takes the bitmap path
     {"small_max": 4096},                        # every owner up to degree 4096 takes the wave path
@@ -62,7 +63,7 @@ def test_tune_batch_multiwindow(graphs):
 
 def test_tune_errors(graphs):
     g = graphs[0][0]
-    for bad in ({"small_max": 5000}, {"spc": 2048}, {"wbits": 9}, {"wbits": 25}, {"small_max": -1}):
+    for bad in ({"small_max": 5000}, {"spc": 2048}, {"wbits": 9}, {"wbits": 25}, {"small_max": -1}, {"flags": 2}):
         with pytest.raises(scan.ScanError) as ei:
             scan.scan_build_index(*device_csr(g), scan.COSINE, 0, tune=bad)
         assert ei.value.status == scan.SCAN_EINVAL, bad
