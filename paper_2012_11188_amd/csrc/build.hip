@@ -331,15 +331,23 @@ __global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
   const int64_t total = tile_first[nrt];
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t lo = 0, hi = nrt;  // last rank tile with tile_first <= b
-      while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (tile_first[mid] <= b) lo = mid;
-        else hi = mid;
+    if (threadIdx.x < kWave) {
+      // the last rank tile with tile_first <= b (tile_first[0] = 0): a 64-way
+      // search by the first wavefront, every lane sampling one rank tile
+      const int lane = threadIdx.x;
+      int64_t lo = 0, cnt = nrt;
+      while (cnt > 1) {
+        const int64_t step = (cnt + kWave - 1) / kWave;
+        const int64_t q = lo + lane * step;
+        const int c = __popcll(__ballot(q < lo + cnt && tile_first[q] <= b));  // >= 1: lane 0
+        const int64_t nlo = lo + (c - 1) * step;
+        cnt = min(step, lo + cnt - nlo);
+        lo = nlo;
       }
-      s_t = lo;
-      s_k = b - tile_first[lo];
+      if (lane == 0) {
+        s_t = lo;
+        s_k = b - tile_first[lo];
+      }
     }
     __syncthreads();
     const RTile r = rt[s_t];
