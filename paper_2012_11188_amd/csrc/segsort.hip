@@ -353,17 +353,28 @@ struct BlockSort {
         if (key_less(s.K[jb], s.I[jb], s.K[ja], s.I[ja])) hi = mid;
         else lo = mid + 1;
       }
+      // The heads of both runs stay in registers; after each output only
+      // the consumed run's next element is read (two LDS reads per output).
       int ia = lo, ib = diag - lo;
+      const int pa0 = lds_pad(a0 + min(ia, w - 1)), pb0 = lds_pad(b0 + min(ib, w - 1));
+      uint64_t ka = s.K[pa0], kb = s.K[pb0];
+      int32_t ra = s.I[pa0], rb = s.I[pb0];
 #pragma unroll
       for (int x = 0; x < ITEMS; ++x) {
-        const int pa = lds_pad(a0 + min(ia, w - 1)), pb = lds_pad(b0 + min(ib, w - 1));
-        const uint64_t ka = s.K[pa], kb = s.K[pb];
-        const int32_t ra = s.I[pa], rb = s.I[pb];
         const bool take_b = ib < w && (ia >= w || key_less(kb, rb, ka, ra));
         k[x] = take_b ? kb : ka;
         id[x] = take_b ? rb : ra;
-        ib += take_b ? 1 : 0;
-        ia += take_b ? 0 : 1;
+        if (x + 1 < ITEMS) {
+          ib += take_b ? 1 : 0;
+          ia += take_b ? 0 : 1;
+          const int pn = take_b ? lds_pad(b0 + min(ib, w - 1)) : lds_pad(a0 + min(ia, w - 1));
+          const uint64_t kn = s.K[pn];
+          const int32_t rn = s.I[pn];
+          ka = take_b ? ka : kn;
+          ra = take_b ? ra : rn;
+          kb = take_b ? kn : kb;
+          rb = take_b ? rn : rb;
+        }
       }
       __syncthreads();
     }
@@ -635,20 +646,30 @@ __global__ __launch_bounds__(kSortBlock) void k_big_merge(
         else
           lo = mid + 1;
       }
+      // heads in registers; only the consumed side's next element is read
+      // (positions clamped to staged entries; an exhausted side is not used)
       int ia = lo, ib = my0 - lo;
+      const int pa0 = lds_pad(na > 0 ? min(ia, na - 1) : 0);
+      const int pb0 = lds_pad(nb > 0 ? na + min(ib, nb - 1) : 0);
+      uint64_t ka = K[pa0], kb = K[pb0];
+      int32_t ra = I[pa0], rb = I[pb0];
 #pragma unroll
       for (int x = 0; x < kMergeItems; ++x) {
-        // clamped to staged entries; a side that is exhausted is not used
-        const int pa = lds_pad(na > 0 ? min(ia, na - 1) : 0);
-        const int pb = lds_pad(nb > 0 ? na + min(ib, nb - 1) : 0);
-        const uint64_t ka = K[pa], kb = K[pb];
-        const int32_t ra = I[pa], rb = I[pb];
         const bool has_a = ia < na, has_b = ib < nb;
         const bool take_a = has_a && (!has_b || key_less(ka, ra, kb, rb));
         rk[x] = take_a ? ka : has_b ? kb : kPadKey;
         ri[x] = take_a ? ra : has_b ? rb : kPadId;
-        ia += take_a ? 1 : 0;
-        ib += (!take_a && has_b) ? 1 : 0;
+        if (x + 1 < kMergeItems) {
+          ia += take_a ? 1 : 0;
+          ib += (!take_a && has_b) ? 1 : 0;
+          const int pn = take_a ? lds_pad(na > 0 ? min(ia, na - 1) : 0) : lds_pad(nb > 0 ? na + min(ib, nb - 1) : 0);
+          const uint64_t kn = K[pn];
+          const int32_t rn = I[pn];
+          ka = take_a ? kn : ka;
+          ra = take_a ? rn : ra;
+          kb = take_a ? kb : kn;
+          rb = take_a ? rb : rn;
+        }
       }
     }
     __syncthreads();
