@@ -317,9 +317,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
 
 constexpr int kBigThreads = 1024;
 constexpr int kUnroll = 4;   // loads in flight per lane
-constexpr int kSeg = 1024;   // ids per work item (rows longer than this are split)
-constexpr int kItemLoads = kSeg / kWave;           // loads per lane per item
-constexpr int kGroups = kSeg / (kWave * kUnroll);  // probe groups per item
+constexpr int kSeg = 1024;   // most ids per work item (rows longer than this are split)
 
 // Word of the owner bitmap holding bit y. The bitmap starts the kernel's
 // dynamic LDS, which starts at LDS address 0 because the kernel has no
@@ -389,6 +387,12 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
   BigShared *sh = (BigShared *)(le_xp + spc + 1);
   const int tid = threadIdx.x, lane = lane_id();
   constexpr bool one_window = kOneWindow;  // the whole id space fits one window
+  // Ids per work item: with several windows the per-window ranges are short
+  // and half-size items measure faster (R-MAT-23: 0.57 against 0.62 s),
+  // with one window full-size ones (R-MAT-20: 5.6 against 5.8 ms).
+  constexpr int kItem = kOneWindow ? kSeg : kSeg / 2;
+  constexpr int kItemLoads = kItem / kWave;
+  constexpr int kGroups = kItem / (kWave * kUnroll);
 
   const int32_t nchunks = pc->big;  // written by k_plan: no host round trip
   for (int i = tid; i < nwords; i += blockDim.x) bm[i] = 0u;
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       int32_t ex = 0;
       if (tid < nlow) {
         const int32_t len = le_b1[tid] - le_b0[tid];
-        ex = len > kSeg ? (len - 1) / kSeg : 0;
+        ex = len > kItem ? (len - 1) / kItem : 0;
       }
       const int32_t xp = block_excl_scan(ex, sh->wsum, &sh->nextra);
       if (tid < nlow) le_xp[tid] = xp;
@@ -521,8 +525,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         e = ee;
         ou = uniform64(le_ou[ee]);
         lim = uniform(le_lim[ee]);
-        lo = uniform(le_b0[ee]) + sg * kSeg;
-        hi = min(uniform(le_b1[ee]), lo + kSeg);
+        lo = uniform(le_b0[ee]) + sg * kItem;
+        hi = min(uniform(le_b1[ee]), lo + kItem);
       };
       // Ids [lo, lo + kSeg) of an item's row are readable through a uniform
       // pointer: into adj, or, within kSeg ids of its end, into `tail`, a
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       // of an item of len ids. Per lane, acc counts the hits (low half) and
       // the ids below h (high half): rows are sorted, so with one window the
       // position of h in the lower neighbour's row is the sum of the latter
-      // over the row's items. Both halves stay below 2^16 (<= kSeg per item).
+      // over the row's items. Both halves stay below 2^16 (<= kItem per item).
       auto probe_group = [&](const int32_t x[kUnroll], int32_t g0, int32_t len, uint32_t &acc) {
         if (g0 + kWave * kUnroll <= len) {
 #pragma unroll
