@@ -41,10 +41,6 @@ __device__ __forceinline__ bool key_less(uint64_t ka, int32_t ia, uint64_t kb, i
 constexpr uint64_t kPadKey = ~0ull;
 constexpr int32_t kPadId = 0x7fffffff;
 
-__device__ __forceinline__ int64_t degree_of(const int64_t *off, int64_t v) {
-  return off[v + 1] - off[v];
-}
-
 // ---------------------------------------------------------------------------
 // Host side helpers.
 

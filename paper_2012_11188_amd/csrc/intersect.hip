@@ -19,6 +19,9 @@
 //                   are tested with one LDS read each, then the bits are
 //                   cleared. Chunks are claimed from a global counter, edges
 //                   inside a chunk by wavefronts from an LDS counter.
+//   k_window_table  (ids spanning several windows) the first position of
+//                   every window in every row, so that chunks read each lower
+//                   neighbour's range in a window instead of searching it.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -48,18 +51,6 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ int32_t wave_sum(int32_t v) {
-#pragma unroll
-  for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
-}
-
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-  for (int m = kWave / 2; m > 0; m >>= 1) v = max(v, __shfl_xor(v, m, kWave));
-  return v;
 }
 
 // Sum over the wavefront with DPP row shifts and row broadcasts
