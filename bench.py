@@ -271,6 +271,36 @@ def closed_loop_queries(scan, torch, ix, n, queries, B):
                         "qps": queries / tb}}
 
 
+def roles_timing(scan, torch, ix, g, count=20):
+    """Hubs and outliers (scan_query_roles) after seeded queries: device time
+    per call (hipEvents) and its bytes, 8 B per neighbour of an unclustered
+    vertex (neighbour id and its membership) + 5 B per vertex (membership read,
+    role written); an upper bound, the scan of a hub stops early."""
+    rng = np.random.default_rng(11)
+    deg = np.diff(g.off)
+    memb = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    roles = torch.empty(g.n, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for _ in range(count):
+        mu, eps = int(rng.integers(2, 17)), (10 + 5 * int(rng.integers(0, 17))) / 100.0
+        scan.scan_query(ix, mu, eps, memb)
+        scan.scan_query_roles(ix, memb, roles)  # warm
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        scan.scan_query_roles(ix, memb, roles)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        m = memb.cpu().numpy()
+        r = roles.cpu().numpy()
+        nbytes = 8 * int(deg[m < 0].sum()) + 5 * g.n
+        rows.append((e0.elapsed_time(e1), nbytes, int((r == 1).sum()), int((r == 2).sum()), mu, eps))
+    rows.sort()
+    ms, nbytes, hubs, outl, mu, eps = rows[len(rows) // 2]
+    return {"calls": count, "ms_p50": ms, "ms_max": rows[-1][0], "at_p50": {"mu": mu, "eps": eps, "hubs": hubs,
+            "outliers": outl, "bytes_bound": nbytes, "gbs_bound": nbytes / (ms * 1e-3) / 1e9}}
+
+
 # ---------------------------------------------------------------------------
 # Workloads
 
@@ -330,6 +360,8 @@ def rmat_workload(args, scan, torch, graphgen):
     if scale == 20 and not args.no_queries:
         extra["query"] = closed_loop_queries(scan, torch, ix, g.n, args.queries, args.query_batch)
         log(f"queries: {extra['query']}")
+        extra["roles"] = roles_timing(scan, torch, ix, g)
+        log(f"roles: {extra['roles']}")
         if not args.no_serve:
             extra["serving"] = serving(scan, torch, ix, g.n, args)
     cpu = None

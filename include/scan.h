@@ -224,6 +224,21 @@ scan_status scan_query_batch(const scan_index *ix, int32_t count, const int32_t 
                              const double *eps, int32_t *memberships, int32_t out_on_device,
                              void *stream);
 
+/* Hubs and outliers among the unclustered vertices (Section 4.3, with the
+ * definitions of Section 2): roles[v] = SCAN_ROLE_CLUSTERED if
+ * memberships[v] >= 0; otherwise SCAN_ROLE_HUB if v's neighbours belong to at
+ * least two distinct clusters, else SCAN_ROLE_OUTLIER (neighbours in one
+ * cluster or in none, isolated vertices included). memberships: DEVICE
+ * int32[n], a query result on this index (labels are compared, so any
+ * labelling with -1 for "unclustered" works); roles: DEVICE uint8[n], written.
+ * Runs on `stream` (NULL: the index's stream), asynchronous, O(m) work.
+ * Errors: SCAN_EINVAL for a null pointer. */
+#define SCAN_ROLE_CLUSTERED 0
+#define SCAN_ROLE_HUB 1
+#define SCAN_ROLE_OUTLIER 2
+scan_status scan_query_roles(const scan_index *ix, const int32_t *memberships, uint8_t *roles,
+                             void *stream);
+
 scan_status scan_index_get_info(const scan_index *ix, scan_index_info *out);
 
 /* Copies one index array to host memory (synchronous). dst_bytes must be at

@@ -61,6 +61,8 @@ def _load():
     lib.oracle_core_order.restype = None
     lib.oracle_query.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, i32, f64, vp, vp]
     lib.oracle_query.restype = ctypes.c_int
+    lib.oracle_roles.argtypes = [i64, vp, vp, vp, vp]
+    lib.oracle_roles.restype = None
     _lib = lib
     return lib
 
@@ -179,3 +181,16 @@ def query(ix: OracleIndex, mu: int, eps: float):
     if rc != 0:
         raise ValueError(f"oracle_query rejected mu={mu} eps={eps}")
     return memb, core
+
+
+ROLE_CLUSTERED, ROLE_HUB, ROLE_OUTLIER = 0, 1, 2
+
+
+def roles(g, memberships: np.ndarray) -> np.ndarray:
+    """Section 4.3: uint8[n], 0 in a cluster, 1 hub (unclustered, neighbours in
+    >= 2 clusters), 2 outlier (unclustered, neighbours in at most one)."""
+    off, adj = _csr(g)
+    memb = np.ascontiguousarray(memberships, dtype=np.int32)
+    out = np.zeros(g.n, np.uint8)
+    _load().oracle_roles(g.n, _p(off), _p(adj), _p(memb), _p(out))
+    return out

@@ -13,7 +13,8 @@
 //   * neighbour order and core order: Section 3.2 and Algorithm 2;
 //   * query: Algorithms 3 (GetCores), 5 (Cluster) and 4 (AssignNonCores) with
 //     the deterministic border rule of Section 7.3.4 (most similar
-//     epsilon-similar core, ties to the lower vertex id).
+//     epsilon-similar core, ties to the lower vertex id);
+//   * hubs and outliers among the unclustered vertices: Section 4.3.
 //
 // Readings where the paper leaves a choice (each also listed in the design
 // notes):
@@ -286,6 +287,27 @@ int oracle_query(int64_t n, const int64_t *off, const int32_t *no_ids, const dou
     if (is_core) is_core[v] = core[v];
   }
   return 0;
+}
+
+// Hubs and outliers (Section 4.3, with the definitions of Section 2): every
+// vertex in a cluster gets role 0; an unclustered vertex (membership -1) is a
+// hub (role 1) if its neighbours belong to at least two distinct clusters,
+// and an outlier (role 2) otherwise (neighbours in one cluster or in none).
+// The neighbours are the open neighbourhood N(v) of the CSR row.
+void oracle_roles(int64_t n, const int64_t *off, const int32_t *adj, const int32_t *memberships,
+                  uint8_t *roles) {
+  for (int64_t v = 0; v < n; ++v) {
+    if (memberships[v] >= 0) {
+      roles[v] = 0;
+      continue;
+    }
+    std::vector<int32_t> clusters;
+    for (int64_t k = off[v]; k < off[v + 1]; ++k)
+      if (memberships[adj[k]] >= 0) clusters.push_back(memberships[adj[k]]);
+    std::sort(clusters.begin(), clusters.end());
+    clusters.erase(std::unique(clusters.begin(), clusters.end()), clusters.end());
+    roles[v] = clusters.size() >= 2 ? 1 : 2;
+  }
 }
 
 }  // extern "C"

@@ -80,7 +80,7 @@ EXPORTS = [
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
     "scan_version", "scan_similarity_values", "scan_index_build_profile", "scan_build_index_ex",
-    "scan_autotune", "scan_segmented_sort",
+    "scan_autotune", "scan_segmented_sort", "scan_query_roles",
 ]
 
 _lib = None
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "scan_query": ([vp, i32, f64, vp], i32),
         "scan_query_ex": ([vp, i32, f64, vp, vp, i32, vp], i32),
         "scan_query_batch": ([vp, i32, vp, vp, vp, i32, vp], i32),
+        "scan_query_roles": ([vp, vp, vp, vp], i32),
         "scan_index_get_info": ([vp, P(_Info)], i32),
         "scan_index_export": ([vp, i32, vp, i64], i32),
         "scan_index_device_ptr": ([vp, i32, P(vp), P(i64)], i32),
@@ -403,6 +404,25 @@ def scan_query_ex(ix: Index, mu: int, eps: float, memberships=None, is_core=None
     _check(lib.scan_query_ex(ix._h, int(mu), float(eps), ctypes.c_void_p(mp if ix.n else 0),
                              ctypes.c_void_p(cp if ix.n else 0), int(out_on_device), ctypes.c_void_p(s)))
     return memberships, is_core
+
+
+ROLE_CLUSTERED, ROLE_HUB, ROLE_OUTLIER = 0, 1, 2
+
+
+def scan_query_roles(ix: Index, memberships, roles=None, stream=None):
+    """Hub / outlier roles (Section 4.3) of a query's memberships (a device
+    int32 tensor of n); returns a device uint8 tensor: ROLE_CLUSTERED,
+    ROLE_HUB or ROLE_OUTLIER per vertex. Asynchronous on `stream`."""
+    torch = _torch()
+    lib = _ready()
+    if memberships.device.type != "cuda" or memberships.dtype != torch.int32 or memberships.numel() != ix.n:
+        raise ValueError("memberships must be a device int32 tensor of n entries")
+    if roles is None:
+        roles = torch.empty(ix.n, dtype=torch.uint8, device=memberships.device)
+    s = _stream_handle(stream)
+    _check(lib.scan_query_roles(ix._h, ctypes.c_void_p(memberships.data_ptr() if ix.n else 0),
+                                ctypes.c_void_p(roles.data_ptr() if ix.n else 0), ctypes.c_void_p(s)))
+    return roles
 
 
 def scan_query_batch(ix: Index, mus, epss, out=None, stream=None, out_on_device: bool = True):

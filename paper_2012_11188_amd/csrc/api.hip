@@ -300,6 +300,16 @@ scan_status scan_query_batch(const scan_index *ix, int32_t count, const int32_t 
   return query_impl(ix, count, mu, eps, memberships, nullptr, out_on_device, (hipStream_t)stream);
 }
 
+scan_status scan_query_roles(const scan_index *ix, const int32_t *memberships, uint8_t *roles,
+                             void *stream) {
+  if (!ix) return fail(SCAN_EINVAL, "null index");
+  if (ix->n == 0) return SCAN_OK;
+  if (!memberships || !roles) return fail(SCAN_EINVAL, "null memberships or roles");
+  launch_roles(ix, memberships, roles, stream ? (hipStream_t)stream : ix->stream);
+  SCAN_HIP_TRY(hipGetLastError());
+  return SCAN_OK;
+}
+
 scan_status scan_index_get_info(const scan_index *ix, scan_index_info *out) {
   if (!ix || !out) return fail(SCAN_EINVAL, "null argument");
   out->n = ix->n;

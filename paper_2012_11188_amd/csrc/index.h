@@ -135,6 +135,8 @@ scan_status alloc_query_slot(const scan_index *ix, QuerySlot *slot, hipStream_t 
 
 // Enqueues the four query kernels for `count` device descriptors.
 void launch_query_kernels(const scan_index *ix, QueryDesc *d, int32_t count, hipStream_t s);
+// Hub / outlier roles of the unclustered vertices of one query's memberships.
+void launch_roles(const scan_index *ix, const int32_t *memb, uint8_t *roles, hipStream_t s);
 QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,
                           uint8_t *is_core);
 void free_query_slot(QuerySlot *slot, hipStream_t s);

@@ -22,6 +22,8 @@
 // for mu carries that same threshold value).
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <cmath>
 #include <vector>
 
@@ -30,6 +32,7 @@
 namespace scan {
 
 constexpr uint8_t kCore = 2, kBorder = 1;
+constexpr uint8_t kRoleClustered = SCAN_ROLE_CLUSTERED, kRoleHub = SCAN_ROLE_HUB, kRoleOutlier = SCAN_ROLE_OUTLIER;
 
 struct IndexView {
   int64_t n, dmax;
@@ -195,6 +198,113 @@ void launch_query_kernels(const scan_index *ix, QueryDesc *d, int32_t count, hip
   k_q_jump<<<gc, 256, 0, s>>>(v, d);
   k_q_output<<<go, 256, 0, s>>>(v, d);
   k_q_reset<<<gc, 256, 0, s>>>(v, d);
+}
+
+// Hubs and outliers (Section 4.3): every unclustered vertex maps its
+// neighbours to their clusters and checks whether two of them differ (the NO
+// row holds the open neighbourhood). A wavefront takes kWave / kRoleGroup
+// consecutive vertices, one per group of kRoleGroup lanes; a group scans its
+// vertex's row kRoleGroup ids per step, reducing the step's smallest and
+// largest cluster label within the group (lane exchanges stay inside the
+// group, whose lanes are active together), and stops at a second cluster.
+// Rows longer than kRoleGroupMax are scanned afterwards by the whole
+// wavefront, kRoleSteps * 64 ids per step. A vertex in a cluster gets role 0
+// without reading its row.
+constexpr int kRoleGroup = 8;
+constexpr int64_t kRoleGroupMax = 512;
+constexpr int kRoleSteps = 8;
+
+__device__ __forceinline__ int32_t group_min(int32_t x) {
+#pragma unroll
+  for (int m = kRoleGroup / 2; m > 0; m >>= 1) x = min(x, __shfl_xor(x, m, kWave));
+  return x;
+}
+__device__ __forceinline__ int32_t group_max(int32_t x) {
+#pragma unroll
+  for (int m = kRoleGroup / 2; m > 0; m >>= 1) x = max(x, __shfl_xor(x, m, kWave));
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_q_roles(IndexView ix, const int32_t *memb, uint8_t *roles) {
+  constexpr int kPerWave = kWave / kRoleGroup;
+  const int lane = threadIdx.x & (kWave - 1), pos = lane % kRoleGroup;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t v0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave * kPerWave; v0 < ix.n;
+       v0 += nw * kPerWave) {
+    const int64_t v = v0 + lane / kRoleGroup;
+    int64_t b = 0, e = 0;
+    bool unclustered = false;
+    if (v < ix.n) {
+      unclustered = memb[v] < 0;
+      b = ix.off[v];
+      e = ix.off[v + 1];
+    }
+    const bool group_row = unclustered && e - b <= kRoleGroupMax;
+    uint8_t role = kRoleClustered;
+    if (group_row) {  // the same for every lane of the group
+      int32_t first = -1;
+      bool hub = false;
+      for (int64_t k0 = b; k0 < e && !hub; k0 += kRoleGroup) {
+        const int64_t k = k0 + pos;
+        const int32_t lab = k < e ? memb[ix.no_ids[k]] : -1;
+        const int32_t lo = group_min(lab >= 0 ? lab : INT_MAX);
+        const int32_t hi = group_max(lab);
+        if (lo != INT_MAX) {
+          if (first < 0) first = lo;
+          hub = lo != first || hi != first;
+        }
+      }
+      role = hub ? kRoleHub : kRoleOutlier;
+    }
+    // long unclustered rows: one at a time by the whole wavefront
+    uint64_t longs = __ballot(unclustered && !group_row && pos == 0);
+    while (longs) {
+      const int src = __ffsll((unsigned long long)longs) - 1;
+      longs &= longs - 1;
+      const int64_t rb = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)b, src) |
+                         ((int64_t)__builtin_amdgcn_readlane((int32_t)(b >> 32), src) << 32);
+      const int64_t re = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)e, src) |
+                         ((int64_t)__builtin_amdgcn_readlane((int32_t)(e >> 32), src) << 32);
+      // kRoleSteps * kWave ids per iteration, all of their loads issued
+      // before the labels are reduced (smallest and largest over the wave)
+      int32_t first = -1;
+      bool hub = false;
+      for (int64_t k0 = rb; k0 < re && !hub; k0 += kRoleSteps * kWave) {  // uniform bounds and exit
+        int32_t w[kRoleSteps];
+#pragma unroll
+        for (int j = 0; j < kRoleSteps; ++j) {
+          const int64_t k = k0 + j * kWave + lane;
+          w[j] = k < re ? ix.no_ids[k] : -1;
+        }
+        int32_t lo = INT_MAX, hi = -1;
+#pragma unroll
+        for (int j = 0; j < kRoleSteps; ++j) {
+          const int32_t lab = w[j] >= 0 ? memb[w[j]] : -1;
+          if (lab >= 0) {
+            lo = min(lo, lab);
+            hi = max(hi, lab);
+          }
+        }
+#pragma unroll
+        for (int m = kWave / 2; m > 0; m >>= 1) {
+          lo = min(lo, __shfl_xor(lo, m, kWave));
+          hi = max(hi, __shfl_xor(hi, m, kWave));
+        }
+        if (lo != INT_MAX) {
+          if (first < 0) first = lo;
+          hub = lo != first || hi != first;
+        }
+      }
+      if (lane / kRoleGroup == src / kRoleGroup) role = hub ? kRoleHub : kRoleOutlier;
+    }
+    if (v < ix.n && pos == 0) roles[v] = role;
+  }
+}
+
+void launch_roles(const scan_index *ix, const int32_t *memb, uint8_t *roles, hipStream_t s) {
+  IndexView v{ix->n, ix->dmax, ix->off, ix->no_ids, ix->no_sim, ix->co_off, ix->co_ids, ix->co_thr};
+  k_q_roles<<<grid_for((ix->n + kWave / kRoleGroup - 1) / (kWave / kRoleGroup) * kWave, 256), 256, 0, s>>>(
+      v, memb, roles);
 }
 
 QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,

@@ -121,6 +121,46 @@ def test_paper_worked_example_and_captions():
     assert sorted(map(sorted, clusters.values())) == [[1, 2, 3, 4], [6, 7, 8, 11]]
     assert memb[5] == memb[9] == memb[10] == -1
     assert memb[11] >= 0 and core[11] == 0
+    # The same caption: the unclustered 5 is a hub, 9 and 10 are outliers
+    # (Section 2 definitions; Section 4.3 computes them).
+    roles = oracle.roles(g, memb)
+    assert roles[5] == oracle.ROLE_HUB and roles[9] == roles[10] == oracle.ROLE_OUTLIER
+    assert all(roles[v] == oracle.ROLE_CLUSTERED for v in (1, 2, 3, 4, 6, 7, 8, 11))
+
+
+def load_expectations(path):
+    """The '#!' lines of a fixture: (mu, eps, memberships, roles)."""
+    out = []
+    for ln in open(path):
+        if ln.startswith("#!"):
+            left, right = ln[2:].split("|")
+            f = left.split()
+            out.append((int(f[0]), float(f[1]), [int(x) for x in f[2:]], [int(x) for x in right.split()]))
+    return out
+
+
+def test_hub_outlier_hand_worked():
+    path = os.path.join(GOLDEN, "hub_outlier_hand.txt")
+    g = load_edge_fixture(path)
+    ix = oracle.build_index(g, oracle.COSINE)
+    cases = load_expectations(path)
+    assert len(cases) == 3
+    for mu, eps, want_memb, want_roles in cases:
+        memb, _ = oracle.query(ix, mu, eps)
+        assert memb.tolist() == want_memb, (mu, eps)
+        assert oracle.roles(g, memb).tolist() == want_roles, (mu, eps)
+
+
+def test_roles_special_cases():
+    # no clusters at all: every vertex is an outlier, isolated ones included
+    g = graphgen.from_edges(5, [(0, 1), (1, 2)])
+    assert oracle.roles(g, np.full(5, -1, np.int32)).tolist() == [2] * 5
+    # a star whose leaves sit in three different clusters: the centre is a hub
+    # whatever the labels' values; with two leaves in one cluster and the
+    # third unclustered it is an outlier
+    g = graphgen.from_edges(4, [(0, 1), (0, 2), (0, 3)])
+    assert oracle.roles(g, np.array([-1, 7, 3, 9], np.int32)).tolist() == [1, 0, 0, 0]
+    assert oracle.roles(g, np.array([-1, 7, 7, -1], np.int32)).tolist() == [2, 0, 0, 2]
 
 
 # --------------------------------------------------------------------------
