@@ -301,6 +301,23 @@ def roles_timing(scan, torch, ix, g, count=20):
             "outliers": outl, "bytes_bound": nbytes, "gbs_bound": nbytes / (ms * 1e-3) / 1e9}}
 
 
+def sweep_timing(scan, torch, ix, dmax, batch=32):
+    """Section 7.3.4's parameter selection on the index: the modularity of
+    every (mu, eps) of the paper's grid (mu = 2..2^18 in powers of two up to
+    dmax + 1, eps = .01 .. .99), as batched queries plus device modularity."""
+    grid = scan.paper_sweep_grid(dmax)
+    mus = np.array([m for m, _ in grid], np.int32)
+    epss = np.array([e for _, e in grid])
+    scan.scan_sweep_modularity(ix, mus[:batch], epss[:batch], batch=batch)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    q = scan.scan_sweep_modularity(ix, mus, epss, batch=batch)
+    wall = time.perf_counter() - t
+    best = int(np.argmax(q))
+    return {"queries": len(grid), "batch": batch, "wall_s": wall, "queries_per_s": len(grid) / wall,
+            "best": {"mu": int(mus[best]), "eps": float(epss[best]), "modularity": float(q[best])}}
+
+
 # ---------------------------------------------------------------------------
 # Workloads
 
@@ -362,6 +379,8 @@ def rmat_workload(args, scan, torch, graphgen):
         log(f"queries: {extra['query']}")
         extra["roles"] = roles_timing(scan, torch, ix, g)
         log(f"roles: {extra['roles']}")
+        extra["sweep"] = sweep_timing(scan, torch, ix, st["dmax"])
+        log(f"sweep: {extra['sweep']}")
         if not args.no_serve:
             extra["serving"] = serving(scan, torch, ix, g.n, args)
     cpu = None

@@ -239,6 +239,27 @@ scan_status scan_query_batch(const scan_index *ix, int32_t count, const int32_t 
 scan_status scan_query_roles(const scan_index *ix, const int32_t *memberships, uint8_t *roles,
                              void *stream);
 
+/* Modularity (Section 7.2, Newman's definition) of one clustering, every
+ * unclustered vertex in a cluster of its own as in Section 7.3.4:
+ *   q = 1/(2m) * sum over ordered pairs (u, v) of (A_uv - d_u d_v / 2m) delta_uv
+ *     = (s_in - sd2 / 2m) / 2m, 2m = nnz,
+ * with s_in (ordered neighbour pairs inside a cluster) and sd2 (sum over
+ * clusters of the squared degree sum) accumulated exactly as integers on
+ * the device; the last step is those two FP64 divisions. memberships: DEVICE
+ * int32[n], labels -1 or in [0, n) (any other value: SCAN_EINVAL). Runs on
+ * `stream` (NULL: the index's stream) and returns when *q (host) is set. */
+scan_status scan_query_modularity(const scan_index *ix, const int32_t *memberships, double *q,
+                                  void *stream);
+
+/* The parameter selection of Section 7.3.4: the modularity (as above) of
+ * the clustering of each (mu[i], eps[i]), i < count (host arrays), run as
+ * batched queries of up to `batch` (1..256) on `stream`; q[i] (host) is
+ * written. Synchronous. Device memory: batch * n * 4 + n * 8 + count * 24
+ * bytes. Errors: SCAN_EINVAL for a null pointer, a bad batch, or an
+ * invalid (mu, eps) (nothing is run then). */
+scan_status scan_sweep_modularity(const scan_index *ix, int32_t count, const int32_t *mu,
+                                  const double *eps, int32_t batch, double *q, void *stream);
+
 scan_status scan_index_get_info(const scan_index *ix, scan_index_info *out);
 
 /* Copies one index array to host memory (synchronous). dst_bytes must be at

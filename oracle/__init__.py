@@ -63,6 +63,10 @@ def _load():
     lib.oracle_query.restype = ctypes.c_int
     lib.oracle_roles.argtypes = [i64, vp, vp, vp, vp]
     lib.oracle_roles.restype = None
+    lib.oracle_modularity_terms.argtypes = [i64, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.oracle_modularity_terms.restype = None
+    lib.oracle_modularity_value.argtypes = [i64, i64, i64]
+    lib.oracle_modularity_value.restype = f64
     _lib = lib
     return lib
 
@@ -194,3 +198,14 @@ def roles(g, memberships: np.ndarray) -> np.ndarray:
     out = np.zeros(g.n, np.uint8)
     _load().oracle_roles(g.n, _p(off), _p(adj), _p(memb), _p(out))
     return out
+
+
+def modularity(g, memberships: np.ndarray):
+    """Section 7.2 modularity with unclustered vertices as singletons
+    (Section 7.3.4): (Q, s_in, sd2), see oracle_modularity_terms."""
+    off, adj = _csr(g)
+    memb = np.ascontiguousarray(memberships, dtype=np.int32)
+    s_in, sd2 = ctypes.c_int64(), ctypes.c_int64()
+    lib = _load()
+    lib.oracle_modularity_terms(g.n, _p(off), _p(adj), _p(memb), ctypes.byref(s_in), ctypes.byref(sd2))
+    return float(lib.oracle_modularity_value(s_in.value, sd2.value, g.nnz)), s_in.value, sd2.value

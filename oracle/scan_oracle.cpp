@@ -310,4 +310,37 @@ void oracle_roles(int64_t n, const int64_t *off, const int32_t *adj, const int32
   }
 }
 
+// Modularity of a clustering (Section 7.2, Newman's definition), with every
+// unclustered vertex (membership -1) in a cluster of its own (Section 7.3.4):
+//   Q = 1/(2m) * sum over ordered pairs (u, v) of (A_uv - d_u d_v / 2m) delta_uv.
+// Grouping the pairs by cluster C gives the two integers returned here:
+//   s_in = sum over u of |{v in N(u) : v in C(u)}|  (ordered pairs inside clusters),
+//   sd2  = sum over clusters of (sum of degrees in C)^2,
+// and Q = (s_in - sd2 / 2m) / 2m with 2m = nnz; oracle_modularity_value does
+// that last step in FP64 (one division inside, one outside).
+void oracle_modularity_terms(int64_t n, const int64_t *off, const int32_t *adj, const int32_t *memberships,
+                             int64_t *s_in, int64_t *sd2) {
+  int64_t in = 0;
+  for (int64_t u = 0; u < n; ++u)
+    if (memberships[u] >= 0)
+      for (int64_t k = off[u]; k < off[u + 1]; ++k)
+        if (memberships[adj[k]] == memberships[u]) ++in;
+  std::vector<int64_t> dsum((size_t)n, 0);  // labels are vertex ids
+  int64_t sq = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t d = off[v + 1] - off[v];
+    if (memberships[v] >= 0) dsum[memberships[v]] += d;
+    else sq += d * d;  // a cluster of its own
+  }
+  for (int64_t c = 0; c < n; ++c) sq += dsum[c] * dsum[c];
+  *s_in = in;
+  *sd2 = sq;
+}
+
+double oracle_modularity_value(int64_t s_in, int64_t sd2, int64_t nnz) {
+  if (nnz == 0) return 0.0;
+  const double two_m = (double)nnz;
+  return ((double)s_in - (double)sd2 / two_m) / two_m;
+}
+
 }  // extern "C"

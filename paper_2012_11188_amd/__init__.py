@@ -80,7 +80,8 @@ EXPORTS = [
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
     "scan_version", "scan_similarity_values", "scan_index_build_profile", "scan_build_index_ex",
-    "scan_autotune", "scan_segmented_sort", "scan_query_roles",
+    "scan_autotune", "scan_segmented_sort", "scan_query_roles", "scan_query_modularity",
+    "scan_sweep_modularity",
 ]
 
 _lib = None
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "scan_query_ex": ([vp, i32, f64, vp, vp, i32, vp], i32),
         "scan_query_batch": ([vp, i32, vp, vp, vp, i32, vp], i32),
         "scan_query_roles": ([vp, vp, vp, vp], i32),
+        "scan_query_modularity": ([vp, vp, P(f64), vp], i32),
+        "scan_sweep_modularity": ([vp, i32, vp, vp, i32, vp, vp], i32),
         "scan_index_get_info": ([vp, P(_Info)], i32),
         "scan_index_export": ([vp, i32, vp, i64], i32),
         "scan_index_device_ptr": ([vp, i32, P(vp), P(i64)], i32),
@@ -423,6 +426,43 @@ def scan_query_roles(ix: Index, memberships, roles=None, stream=None):
     _check(lib.scan_query_roles(ix._h, ctypes.c_void_p(memberships.data_ptr() if ix.n else 0),
                                 ctypes.c_void_p(roles.data_ptr() if ix.n else 0), ctypes.c_void_p(s)))
     return roles
+
+
+def scan_query_modularity(ix: Index, memberships, stream=None) -> float:
+    """Section 7.2 modularity of a clustering (a device int32 tensor of n
+    memberships; unclustered vertices are singletons). Synchronous."""
+    torch = _torch()
+    lib = _ready()
+    if memberships.device.type != "cuda" or memberships.dtype != torch.int32 or memberships.numel() != ix.n:
+        raise ValueError("memberships must be a device int32 tensor of n entries")
+    q = ctypes.c_double()
+    _check(lib.scan_query_modularity(ix._h, ctypes.c_void_p(memberships.data_ptr() if ix.n else 0),
+                                     ctypes.byref(q), ctypes.c_void_p(_stream_handle(stream))))
+    return q.value
+
+
+def paper_sweep_grid(dmax: int | None = None):
+    """The parameter set of Section 7.3.4: mu in {2, 4, ..., 2^18} x eps in
+    {.01, ..., .99} (eps built as k / 100.0); mu above dmax + 1 is dropped
+    when dmax is given (no cores there)."""
+    mus = [1 << k for k in range(1, 19)]
+    if dmax is not None:
+        mus = [m for m in mus if m <= dmax + 1]
+    return [(m, k / 100.0) for m in mus for k in range(1, 100)]
+
+
+def scan_sweep_modularity(ix: Index, mus, epss, batch: int = 32, stream=None) -> np.ndarray:
+    """Modularity of the clustering of every (mus[i], epss[i]), run as batched
+    queries (Section 7.3.4's parameter selection). Synchronous."""
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    epss = np.ascontiguousarray(epss, dtype=np.float64)
+    if mus.shape != epss.shape or mus.ndim != 1:
+        raise ValueError("mus and epss must be 1-d of one length")
+    q = np.zeros(len(mus), np.float64)
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data if a.size else 0)  # noqa: E731
+    _check(_ready().scan_sweep_modularity(ix._h, len(mus), ptr(mus), ptr(epss), int(batch), ptr(q),
+                                          ctypes.c_void_p(_stream_handle(stream))))
+    return q
 
 
 def scan_query_batch(ix: Index, mus, epss, out=None, stream=None, out_on_device: bool = True):

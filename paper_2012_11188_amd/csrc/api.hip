@@ -310,6 +310,63 @@ scan_status scan_query_roles(const scan_index *ix, const int32_t *memberships, u
   return SCAN_OK;
 }
 
+scan_status scan_query_modularity(const scan_index *ix, const int32_t *memberships, double *q, void *stream) {
+  if (!ix || !q) return fail(SCAN_EINVAL, "null index or q");
+  if (ix->n > 0 && !memberships) return fail(SCAN_EINVAL, "null memberships");
+  *q = 0.0;
+  if (ix->n == 0) return SCAN_OK;
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  DevArena tmp(s);
+  int64_t *dsum, *terms;
+  SCAN_TRY(tmp.alloc(&dsum, ix->n));
+  SCAN_TRY(tmp.alloc(&terms, 3));
+  zero64(dsum, ix->n, s);
+  zero64(terms, 3, s);
+  launch_modularity_terms(ix, memberships, dsum, terms, s);
+  int64_t h[3];
+  SCAN_HIP_TRY(hipMemcpyAsync(h, terms, sizeof(h), hipMemcpyDeviceToHost, s));
+  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  if (h[2]) return fail(SCAN_EINVAL, "%lld memberships outside [-1, n)", (long long)h[2]);
+  *q = modularity_value(h[0], h[1], ix->nnz);
+  return SCAN_OK;
+}
+
+scan_status scan_sweep_modularity(const scan_index *ix, int32_t count, const int32_t *mu, const double *eps,
+                                  int32_t batch, double *q, void *stream) {
+  if (!ix) return fail(SCAN_EINVAL, "null index");
+  if (count < 0) return fail(SCAN_EINVAL, "negative count");
+  if (count == 0) return SCAN_OK;
+  if (!mu || !eps || !q) return fail(SCAN_EINVAL, "null argument");
+  if (batch < 1 || batch > 256) return fail(SCAN_EINVAL, "batch %d outside 1..256", batch);
+  for (int32_t i = 0; i < count; ++i) SCAN_TRY(check_query(ix, mu[i], eps[i]));
+  const int64_t n = ix->n;
+  if (n == 0) {
+    for (int32_t i = 0; i < count; ++i) q[i] = 0.0;
+    return SCAN_OK;
+  }
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  const int32_t B = std::min(batch, count);
+  DevArena tmp(s);
+  int32_t *memb;
+  int64_t *dsum, *terms;
+  SCAN_TRY(tmp.alloc(&memb, (int64_t)B * n));
+  SCAN_TRY(tmp.alloc(&dsum, n));
+  SCAN_TRY(tmp.alloc(&terms, (int64_t)3 * count));
+  zero64(dsum, n, s);
+  zero64(terms, (int64_t)3 * count, s);
+  for (int32_t i = 0; i < count; i += B) {
+    const int32_t c = std::min(B, count - i);
+    SCAN_TRY(query_impl(ix, c, mu + i, eps + i, memb, nullptr, 1, s));
+    for (int32_t j = 0; j < c; ++j) launch_modularity_terms(ix, memb + (int64_t)j * n, dsum, terms + 3 * (int64_t)(i + j), s);
+    SCAN_HIP_TRY(hipGetLastError());
+  }
+  std::vector<int64_t> h((size_t)3 * count);
+  SCAN_HIP_TRY(hipMemcpyAsync(h.data(), terms, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < count; ++i) q[i] = modularity_value(h[3 * i], h[3 * i + 1], ix->nnz);
+  return SCAN_OK;
+}
+
 scan_status scan_index_get_info(const scan_index *ix, scan_index_info *out) {
   if (!ix || !out) return fail(SCAN_EINVAL, "null argument");
   out->n = ix->n;

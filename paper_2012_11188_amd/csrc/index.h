@@ -135,6 +135,13 @@ scan_status alloc_query_slot(const scan_index *ix, QuerySlot *slot, hipStream_t 
 
 // Enqueues the four query kernels for `count` device descriptors.
 void launch_query_kernels(const scan_index *ix, QueryDesc *d, int32_t count, hipStream_t s);
+// Modularity terms (quality.hip): terms[0] += s_in, terms[1] += sd2 for one
+// clustering; dsum (int64[n]) must be zero on entry and is zero on return.
+void zero64(int64_t *p, int64_t count, hipStream_t s);
+void launch_modularity_terms(const scan_index *ix, const int32_t *memb, int64_t *dsum, int64_t *terms,
+                             hipStream_t s);
+double modularity_value(int64_t s_in, int64_t sd2, int64_t nnz);
+
 // Hub / outlier roles of the unclustered vertices of one query's memberships.
 void launch_roles(const scan_index *ix, const int32_t *memb, uint8_t *roles, hipStream_t s);
 QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,

@@ -391,3 +391,52 @@ def test_query_props_match_oracle(seed):
             w, wc = expected_query(g.off, g.adj, ix.sim, ix.no_ids, ix.no_sim, mu, eps)
             assert np.array_equal(wc, core.astype(bool)), (mu, eps)
             assert np.array_equal(w, memb), (mu, eps)
+
+
+# --------------------------------------------------------------------------
+# Modularity (Section 7.2; unclustered vertices as singletons, Section 7.3.4)
+
+
+def modularity_by_definition(g, memb):
+    """The printed double sum over ordered vertex pairs, in exact rationals."""
+    from fractions import Fraction
+
+    n = g.n
+    deg = np.diff(g.off)
+    adj = [set(g.adj[g.off[v]:g.off[v + 1]].tolist()) for v in range(n)]
+    cl = [int(m) if m >= 0 else -(v + 1) for v, m in enumerate(memb)]  # singletons get distinct labels
+    two_m = int(g.nnz)
+    total = Fraction(0)
+    for u in range(n):
+        for v in range(n):
+            if cl[u] == cl[v]:
+                total += Fraction(int(v in adj[u])) - Fraction(int(deg[u]) * int(deg[v]), two_m)
+    return total / two_m
+
+
+def test_modularity_closed_forms():
+    # two disjoint triangles, one cluster each: 2 * (3/6 - (6/12)^2) = 1/2
+    g = graphgen.from_edges(6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)])
+    assert oracle.modularity(g, np.array([0, 0, 0, 3, 3, 3], np.int32))[0] == 0.5
+    # a connected graph as one cluster: 1 - 1 = 0
+    g = graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    assert oracle.modularity(g, np.zeros(4, np.int32))[0] == 0.0
+    # every vertex on its own: -sum d^2 / (2m)^2 = -(1 + 4 + 4 + 1) / 36
+    q, s_in, sd2 = oracle.modularity(g, np.full(4, -1, np.int32))
+    assert (s_in, sd2) == (0, 10) and q == -10 / 36
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_modularity_matches_the_printed_sum(seed):
+    from fractions import Fraction
+
+    rng = np.random.default_rng(seed)
+    g = graphgen.random_graph(9 + seed, 0.35, seed=seed + 40)
+    if g.nnz == 0:
+        return
+    memb = rng.integers(-1, 3, g.n).astype(np.int32)
+    memb = np.where(memb >= 0, memb * 2, -1).astype(np.int32)  # labels 0, 2, 4 or unclustered
+    q, s_in, sd2 = oracle.modularity(g, memb)
+    exact = modularity_by_definition(g, memb)
+    assert (Fraction(s_in) - Fraction(sd2, g.nnz)) / g.nnz == exact
+    assert abs(Fraction(q) - exact) <= Fraction(4 * 2 ** -52) * max(1, abs(exact))
