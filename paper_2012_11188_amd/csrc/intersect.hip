@@ -307,7 +307,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
 // Big owners: persistent workgroups with an LDS bitmap window.
 
 constexpr int kBigThreads = 1024;
-constexpr int kUnroll = 4;   // loads in flight per lane
+constexpr int kUnroll = 4;   // ids per lane per probe group
 constexpr int kSeg = 1024;   // most ids per work item (rows longer than this are split)
 
 // Word of the owner bitmap holding bit y. The bitmap starts the kernel's
@@ -359,8 +359,8 @@ __device__ __forceinline__ int64_t wave_lower_bound(const int32_t *row, int64_t 
 template <bool kOneWindow>
 __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     const BigChunk *chunks, PlanCounts *pc, int spc, int wbits, int64_t n,
-    const int64_t *off, const int32_t *deg, const int32_t *adj, int64_t nnz, const int32_t *tail,
-    int64_t tail0, const int32_t *wt, int32_t nwin, int kind, double *sims, int32_t *counts) {
+    const int64_t *off, const int32_t *deg, const int32_t *adj, const int32_t *wt, int32_t nwin, int kind,
+    double *sims, int32_t *counts) {
   extern __shared__ unsigned char smem[];
   const int64_t W = (int64_t)1 << wbits;
   const int nwords = (int)(W >> 5);
@@ -372,8 +372,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
   int32_t *le_cnt = le_du + spc;
   int32_t *le_b0 = le_cnt + spc;
   int32_t *le_b1 = le_b0 + spc;  // end of the range in the current window (cursor)
-  int32_t *le_lim = le_b1 + spc;  // largest item start whose kSeg ids lie inside adj
-  int32_t *le_u = le_lim + spc;   // the lower neighbour
+  int32_t *le_u = le_b1 + spc;    // the lower neighbour
   int32_t *le_xp = le_u + spc;    // [spc + 1] exclusive prefix of extra segments
   BigShared *sh = (BigShared *)(le_xp + spc + 1);
   const int tid = threadIdx.x, lane = lane_id();
@@ -426,7 +425,6 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         le_ou[k] = off[u];
         le_cnt[k] = 0;
         le_lt[k] = 0;
-        le_lim[k] = (int32_t)max((int64_t)-1, min((int64_t)INT32_MAX, nnz - kSeg - off[u]));
         le_b0[k] = 0;
         le_b1[k] = one_window ? du : 0;
       }
@@ -481,19 +479,15 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       if (tid == 0) sh->next = 0;
       __syncthreads();
       const int32_t nitems = nlow + uniform(sh->nextra);
-      // Software pipeline over work items: the next item is claimed and its
-      // first kWave*kUnroll ids are requested before the current item's ids
-      // are probed, so two items' loads are in flight per wavefront.
-      // Every lane adds 1 (a uniform operand, which the compiler folds into
+      // Work items are claimed from the LDS counter. Every lane adds 1 (a uniform operand, which the compiler folds into
       // one atomic of the active-lane count), so a claim advances the
       // counter by kWave and the item index is the old value / kWave.
-      auto claim = [&](int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou, int32_t &lim) {
+      auto claim = [&](int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou) {
         const int32_t j = uniform(atomicAdd(&sh->next, 1)) / kWave;
         if (j >= nitems) {
           e = -1;
           lo = hi = 0;
           ou = 0;
-          lim = INT32_MAX;
           return;
         }
         int32_t ee = j, sg = 0;
@@ -515,22 +509,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         }
         e = ee;
         ou = uniform64(le_ou[ee]);
-        lim = uniform(le_lim[ee]);
         lo = uniform(le_b0[ee]) + sg * kItem;
         hi = min(uniform(le_b1[ee]), lo + kItem);
-      };
-      // Ids [lo, lo + kSeg) of an item's row are readable through a uniform
-      // pointer: into adj, or, within kSeg ids of its end, into `tail`, a
-      // zero-padded copy of adj[tail0, nnz). Loads are then unmasked and
-      // address the row as scalar base + lane offset + immediate; ids past
-      // the item's end are masked in the probe. The choice is a 32-bit
-      // compare with the edge's limit (le_lim), i.e. scalar code.
-      auto item_ptr = [&](int64_t ou, int32_t lo, int32_t lim) -> const int32_t * {
-        return lo <= lim ? adj + ou + lo : tail + (ou + lo - tail0);
-      };
-      auto fetch = [&](int32_t x[kUnroll], const int32_t *rp) {
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) x[k] = rp[k * kWave + lane];
       };
       // Probes the group of kWave * kUnroll ids that starts at position g0
       // of an item of len ids. Per lane, acc counts the hits (low half) and
@@ -558,14 +538,20 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       };
       // Whole items are requested one item ahead, and the loop body is
       // unrolled twice so the two register sets swap roles without register
-      // copies (a copy waits for its load). Every group of an item is
-      // loaded: a fixed count keeps the waits exact (the compiler waits for
-      // an item's loads by counting the loads issued after them); a group
-      // past the item's end re-reads the first group's ids, which are
-      // cached, instead of fetching new lines, and is not probed.
-      auto fetch_item = [&](int32_t x[kItemLoads], const int32_t *rp, int32_t len) {
+      // copies (a copy waits for its load). Every load of an item is
+      // issued: a fixed count keeps the waits exact (the compiler waits for
+      // an item's loads by counting the loads issued after them). The loads
+      // are raw buffer loads over a resource of exactly the item's bytes, so
+      // lanes past its end read 0 without touching memory (no line is
+      // fetched for them, and no bound check or mask is needed; the probe
+      // masks those lanes). Addressing is scalar base + lane offset +
+      // immediate: no vector instruction per load.
+      auto fetch_item = [&](int32_t x[kItemLoads], int64_t ou, int32_t lo, int32_t len) {
+        // resource word 3: DATA_FORMAT 32 (a valid format enables the buffer)
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(adj + ou + lo), (short)0, len * 4, 0x00020000);
 #pragma unroll
-        for (int c = 0; c < kGroups; ++c) fetch(x + c * kUnroll, len > c * kWave * kUnroll ? rp + c * kWave * kUnroll : rp);
+        for (int j = 0; j < kItemLoads; ++j) x[j] = __builtin_amdgcn_raw_buffer_load_b32(r, lane * 4 + j * kWave * 4, 0, 0);
       };
       auto probe_item = [&](const int32_t x[kItemLoads], int32_t e, int32_t len) {
         uint32_t acc = 0;
@@ -582,20 +568,20 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       };
       // Items are claimed one step further ahead, after a probe has freed
       // its registers, so no claim waits on loads in flight.
-      int32_t ea, loa, hia, lima, eb, lob, hib, limb;
+      int32_t ea, loa, hia, eb, lob, hib;
       int64_t oua, oub;
       int32_t xa[kItemLoads], xb[kItemLoads];
-      claim(ea, loa, hia, oua, lima);
-      fetch_item(xa, item_ptr(oua, loa, lima), hia - loa);
-      claim(eb, lob, hib, oub, limb);
+      claim(ea, loa, hia, oua);
+      fetch_item(xa, oua, loa, hia - loa);
+      claim(eb, lob, hib, oub);
       while (ea >= 0) {
-        fetch_item(xb, item_ptr(oub, lob, limb), hib - lob);
+        fetch_item(xb, oub, lob, hib - lob);
         probe_item(xa, ea, hia - loa);
-        claim(ea, loa, hia, oua, lima);
+        claim(ea, loa, hia, oua);
         if (eb < 0) break;
-        fetch_item(xa, item_ptr(oua, loa, lima), hia - loa);
+        fetch_item(xa, oua, loa, hia - loa);
         probe_item(xb, eb, hib - lob);
-        claim(eb, lob, hib, oub, limb);
+        claim(eb, lob, hib, oub);
       }
       __syncthreads();
       for (int64_t i = p + tid; i < pe; i += blockDim.x) {
@@ -661,7 +647,7 @@ __global__ __launch_bounds__(256) void k_window_table(const int64_t *off, const 
 constexpr size_t kMaxWindowTable = (size_t)4 << 30;
 
 static size_t big_lds_bytes(int wbits, int spc) {
-  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 4 * 9) + 4 + sizeof(BigShared);
+  return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 4 * 8) + 4 + sizeof(BigShared);
 }
 
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
@@ -728,12 +714,6 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   }
   if (stats && stats->ev_mid) (void)hipEventRecord(stats->ev_mid, s);
   if (h.big) {
-    // the last kSeg ids of adj, zero-padded to 2 * kSeg (see k_big_owner)
-    const int64_t tail0 = nnz > kSeg ? nnz - kSeg : 0;
-    int32_t *tail;
-    SCAN_TRY(tmp.alloc(&tail, 2 * kSeg));
-    SCAN_HIP_TRY(hipMemsetAsync(tail, 0, 2 * kSeg * sizeof(int32_t), s));
-    SCAN_HIP_TRY(hipMemcpyAsync(tail, adj + tail0, (nnz - tail0) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     size_t lds = big_lds_bytes(wbits, cfg.spc);
     const bool one = n <= ((int64_t)1 << wbits);
     // Several windows: each row's window starts come from a table (one
@@ -755,11 +735,11 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (size_t)lds_max / lds));
     const int grid = (int)std::min<int64_t>((int64_t)cus * per_cu, h.big);
     if (one)
-      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nnz,
-                                                       tail, tail0, nullptr, nwin, kind, sims, counts);
+      k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nullptr,
+                                                       nwin, kind, sims, counts);
     else
-      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nnz,
-                                                        tail, tail0, wt, nwin, kind, sims, counts);
+      k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, wt,
+                                                        nwin, kind, sims, counts);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);
