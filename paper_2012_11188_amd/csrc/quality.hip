@@ -15,14 +15,12 @@
 
 namespace scan {
 
-namespace {
-
 constexpr int kModThreads = 256;
 constexpr int kModGroup = 8;          // lanes per vertex
 constexpr int64_t kModGroupMax = 512;  // longer rows: the whole wavefront
 constexpr int kModSteps = 8;
 
-__device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *wsum) {
+static __device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *wsum) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
   for (int m = kWave / 2; m > 0; m >>= 1) {
@@ -116,8 +114,6 @@ __global__ void k_zero64(int64_t *p, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
 }
-
-}  // namespace
 
 void zero64(int64_t *p, int64_t count, hipStream_t s) {
   if (count > 0) k_zero64<<<grid_for(count, 256, 4096), 256, 0, s>>>(p, count);
