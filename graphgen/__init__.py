@@ -64,6 +64,9 @@ def _load():
     lib.gg_draw.restype = ctypes.c_uint64
     lib.gg_unit.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.gg_unit.restype = ctypes.c_double
+    lib.gg_edge_weights.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    lib.gg_edge_weights.restype = None
     lib.gg_degree_stats.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p] + [P(ctypes.c_int64)] * 4
     lib.gg_degree_stats.restype = None
     lib.gg_owner_split.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
@@ -145,6 +148,18 @@ def draw(seed: int, ctr: int) -> int:
 
 def unit(seed: int, ctr: int) -> float:
     return float(_load().gg_unit(seed, ctr))
+
+
+def edge_weights(g: Graph, seed: int, lo: float = 0.05, hi: float = 1.0) -> np.ndarray:
+    """float64[nnz] edge weights parallel to g.adj, uniform in [lo, hi) with
+    full 53-bit mantissas, equal for both directions of an edge."""
+    lib = _load()
+    off = np.ascontiguousarray(g.off, dtype=np.int64)
+    adj = np.ascontiguousarray(g.adj, dtype=np.int32)
+    w = np.zeros(g.nnz, np.float64)
+    if g.nnz:
+        lib.gg_edge_weights(g.n, off.ctypes.data, adj.ctypes.data, seed, lo, hi, w.ctypes.data)
+    return w
 
 
 def degree_stats(g: Graph) -> dict:

@@ -59,6 +59,18 @@ typedef struct {
 } gg_csr;
 
 uint64_t gg_draw(uint64_t seed, uint64_t ctr) { return draw(seed, ctr); }
+
+// Edge weights parallel to adj, the same for both directions of an edge:
+// w = lo + (hi - lo) * unit(seed, min(u, v) * n + max(u, v)).
+void gg_edge_weights(int64_t n, const int64_t *off, const int32_t *adj, uint64_t seed, double lo,
+                     double hi, double *w) {
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t s = off[u]; s < off[u + 1]; ++s) {
+      const int64_t v = adj[s];
+      const uint64_t key = (uint64_t)std::min<int64_t>(u, v) * (uint64_t)n + (uint64_t)std::max<int64_t>(u, v);
+      w[s] = lo + (hi - lo) * unit(seed, key);
+    }
+}
 double gg_unit(uint64_t seed, uint64_t ctr) { return unit(seed, ctr); }
 
 void gg_free(gg_csr *g) {

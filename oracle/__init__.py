@@ -27,6 +27,7 @@ _lib = None
 
 COSINE = 0
 JACCARD = 1
+WEIGHTED_COSINE = 2
 
 
 def build() -> str:
@@ -67,6 +68,12 @@ def _load():
     lib.oracle_modularity_terms.restype = None
     lib.oracle_modularity_value.argtypes = [i64, i64, i64]
     lib.oracle_modularity_value.restype = f64
+    lib.oracle_weighted_similarities.argtypes = [i64, vp, vp, vp, i32, vp]
+    lib.oracle_weighted_similarities.restype = None
+    lib.oracle_weighted_edge_similarity.argtypes = [vp, vp, vp, i64, i64]
+    lib.oracle_weighted_edge_similarity.restype = f64
+    lib.oracle_weighted_square_sum.argtypes = [vp, vp, vp, i64]
+    lib.oracle_weighted_square_sum.restype = f64
     _lib = lib
     return lib
 
@@ -173,6 +180,54 @@ def build_index(g, kind: int = COSINE, threads: int = 1) -> OracleIndex:
     no_ids, no_sim = neighbor_order(g, sim, threads)
     co_off, co_ids, co_thr = core_order(g, no_sim, dmax, threads)
     return OracleIndex(g.n, off, dmax, kind, counts, sim, no_ids, no_sim, co_off, co_ids, co_thr)
+
+
+def _weights(g, w) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != (g.nnz,):
+        raise ValueError(f"weights must have nnz = {g.nnz} entries, got {w.shape}")
+    return w
+
+
+def weighted_similarities(g, w: np.ndarray, threads: int = 1) -> np.ndarray:
+    """Section 3.1 weighted cosine of every edge, per CSR slot (w parallel to adj)."""
+    off, adj = _csr(g)
+    w = _weights(g, w)
+    sim = np.zeros(g.nnz, np.float64)
+    _load().oracle_weighted_similarities(g.n, _p(off), _p(adj), _p(w), threads, _p(sim))
+    return sim
+
+
+def weighted_edge_similarity(g, w: np.ndarray, u: int, v: int) -> float:
+    off, adj = _csr(g)
+    return float(_load().oracle_weighted_edge_similarity(_p(off), _p(adj), _p(_weights(g, w)), u, v))
+
+
+def weighted_edge_similarities(g, w: np.ndarray, us: np.ndarray, vs: np.ndarray) -> np.ndarray:
+    off, adj = _csr(g)
+    w = _weights(g, w)
+    lib = _load()
+    po, pa, pw = _p(off), _p(adj), _p(w)
+    return np.array([lib.oracle_weighted_edge_similarity(po, pa, pw, u, v)
+                     for u, v in zip(us.tolist(), vs.tolist())], np.float64)
+
+
+def weighted_square_sum(g, w: np.ndarray, v: int) -> float:
+    """Sum of w(v, x)^2 over the closed neighbourhood of v (w(v, v) = 1)."""
+    off, adj = _csr(g)
+    return float(_load().oracle_weighted_square_sum(_p(off), _p(adj), _p(_weights(g, w)), v))
+
+
+def build_index_weighted(g, w: np.ndarray, threads: int = 1) -> OracleIndex:
+    """Algorithms 1 and 2 with the weighted cosine; counts are not defined
+    for it (all zero here)."""
+    off, _ = _csr(g)
+    dmax = int(_load().oracle_max_degree(g.n, _p(off)))
+    sim = weighted_similarities(g, w, threads)
+    no_ids, no_sim = neighbor_order(g, sim, threads)
+    co_off, co_ids, co_thr = core_order(g, no_sim, dmax, threads)
+    return OracleIndex(g.n, off, dmax, WEIGHTED_COSINE, np.zeros(g.nnz, np.int32), sim, no_ids, no_sim,
+                       co_off, co_ids, co_thr)
 
 
 def query(ix: OracleIndex, mu: int, eps: float):

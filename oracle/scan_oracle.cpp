@@ -14,7 +14,10 @@
 //   * query: Algorithms 3 (GetCores), 5 (Cluster) and 4 (AssignNonCores) with
 //     the deterministic border rule of Section 7.3.4 (most similar
 //     epsilon-similar core, ties to the lower vertex id);
-//   * hubs and outliers among the unclustered vertices: Section 4.3.
+//   * hubs and outliers among the unclustered vertices: Section 4.3;
+//   * weighted cosine (Section 3.1): w(x, x) = 1, closed-neighbourhood sums
+//     taken term by term in ascending vertex id, similarity =
+//     dot / sqrt(S_u * S_v) with S the sums of squared weights.
 //
 // Readings where the paper leaves a choice (each also listed in the design
 // notes):
@@ -42,6 +45,7 @@
 #include <cstring>
 #include <deque>
 #include <thread>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -104,6 +108,51 @@ int64_t common_open_neighbours(const int64_t *off, const int32_t *adj, int64_t u
 double similarity(int kind, int64_t c, int64_t a_u, int64_t a_v) {
   if (kind == 0) return (double)c / std::sqrt((double)a_u * (double)a_v);
   return (double)c / (double)(a_u + a_v - c);
+}
+
+// Weighted cosine (Section 3.1, the measure Algorithm 1 is written for).
+// w(u, x) for x in N(u) is the weight in u's CSR slot for x, and w(x, x) = 1.
+// N[v] as (id, weight) pairs in ascending id, v itself included.
+std::vector<std::pair<int32_t, double>> closed_row(const int64_t *off, const int32_t *adj,
+                                                   const double *w, int64_t v) {
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t s = off[v]; s < off[v + 1]; ++s) row.push_back({adj[s], w[s]});
+  row.push_back({(int32_t)v, 1.0});
+  std::sort(row.begin(), row.end());
+  return row;
+}
+
+// Sum of w(v, x)^2 over N[v], terms added one by one in ascending x (the
+// paper fixes no order; this one is the reading both implementations follow).
+double closed_square_sum(const std::vector<std::pair<int32_t, double>> &row) {
+  double acc = 0.0;
+  for (const auto &e : row) acc += e.second * e.second;
+  return acc;
+}
+
+// Sum of w(u, x) w(v, x) over x in N[u] ∩ N[v], in ascending x.
+double closed_weighted_dot(const std::vector<std::pair<int32_t, double>> &a,
+                           const std::vector<std::pair<int32_t, double>> &b) {
+  double acc = 0.0;
+  size_t i = 0, j = 0;
+  while (i < a.size() && j < b.size()) {
+    if (a[i].first < b[j].first) ++i;
+    else if (a[i].first > b[j].first) ++j;
+    else {
+      acc += a[i].second * b[j].second;
+      ++i;
+      ++j;
+    }
+  }
+  return acc;
+}
+
+// The dot product over the square root of the product of the two square sums
+// (one IEEE multiply, sqrt and divide): with every weight 1 the sums are c,
+// a_u and a_v exactly, so this is the unweighted cosine bit for bit.
+double weighted_cosine(const int64_t *off, const int32_t *adj, const double *w, int64_t u, int64_t v) {
+  const auto ru = closed_row(off, adj, w, u), rv = closed_row(off, adj, w, v);
+  return closed_weighted_dot(ru, rv) / std::sqrt(closed_square_sum(ru) * closed_square_sum(rv));
 }
 
 // Sort key for both orders: similarity descending, then vertex id ascending.
@@ -172,6 +221,32 @@ double oracle_edge_similarity(const int64_t *off, const int32_t *adj, int32_t ki
   int64_t c = common_open_neighbours(off, adj, u, v) + 2;
   if (count) *count = (int32_t)c;
   return similarity(kind, c, degree(off, u) + 1, degree(off, v) + 1);
+}
+
+// Algorithm 1 (weighted cosine): every undirected edge {u, v}, u < v, gets
+// its similarity in both CSR slots. w is parallel to adj.
+void oracle_weighted_similarities(int64_t n, const int64_t *off, const int32_t *adj, const double *w,
+                                  int32_t threads, double *sim) {
+  parallel_for_dynamic(n, threads, [&](int64_t u) {
+    for (int64_t s = off[u]; s < off[u + 1]; ++s) {
+      int64_t v = adj[s];
+      if (v < u) continue;
+      const double x = weighted_cosine(off, adj, w, u, v);
+      int64_t m = std::lower_bound(adj + off[v], adj + off[v + 1], (int32_t)u) - adj;
+      sim[s] = x;
+      sim[m] = x;
+    }
+  });
+}
+
+double oracle_weighted_edge_similarity(const int64_t *off, const int32_t *adj, const double *w, int64_t u,
+                                       int64_t v) {
+  return weighted_cosine(off, adj, w, u, v);
+}
+
+// Sum of w(v, x)^2 over N[v] (the square of Algorithm 1's norm of v).
+double oracle_weighted_square_sum(const int64_t *off, const int32_t *adj, const double *w, int64_t v) {
+  return closed_square_sum(closed_row(off, adj, w, v));
 }
 
 // Algorithm 2, MakeNeighborOrder: each row sorted by non-increasing
