@@ -52,7 +52,9 @@ typedef enum {
   SCAN_EBUSY = -5    /* server admission refused: no slot or memory        */
 } scan_status;
 
-typedef enum { SCAN_SIM_COSINE = 0, SCAN_SIM_JACCARD = 1 } scan_sim_kind;
+/* SCAN_SIM_WEIGHTED_COSINE (Section 3.1's weighted form) is built only by
+ * scan_build_index_weighted, which takes the edge weights. */
+typedef enum { SCAN_SIM_COSINE = 0, SCAN_SIM_JACCARD = 1, SCAN_SIM_WEIGHTED_COSINE = 2 } scan_sim_kind;
 
 /* Build flags. */
 enum {
@@ -160,6 +162,24 @@ scan_status scan_build_index(const scan_csr *g, scan_sim_kind kind, uint32_t fla
  * scan_build_index; on error no index is returned. */
 scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_kind kind,
                                    uint32_t flags, void *stream, scan_index **outs);
+
+/* Builds the index of graph g under the weighted cosine similarity of
+ * Section 3.1 (the measure Algorithm 1 is written for):
+ *   sigma(u, v) = D / sqrt(S_u * S_v),  D = sum over x in N[u] ∩ N[v] of
+ *   w(u, x) w(v, x),  S_v = sum over x in N[v] of w(v, x)^2,
+ * over closed neighbourhoods with w(x, x) = 1. weights[k] (nnz doubles,
+ * parallel to g->adj, host or device like the graph) is w(u, adj[k]) for the
+ * row u holding slot k; the two directions of an edge may differ. Every sum
+ * adds its terms one by one in ascending vertex id, so the result is one
+ * fixed FP64 value per edge; with all weights 1 the index equals the
+ * SCAN_SIM_COSINE one bit for bit. Neighbour order, core order and queries are
+ * as for the other kinds; the index has no intersection counts. The weights
+ * must stay valid until the stream reaches the end of the build.
+ * Errors: as scan_build_index, plus SCAN_EINVAL for a null weights pointer
+ * with nnz > 0 or SCAN_KEEP_COUNTS, and SCAN_EGRAPH (SCAN_VALIDATE only) for a
+ * weight that is not finite. */
+scan_status scan_build_index_weighted(const scan_csr *g, const double *weights, uint32_t flags,
+                                      void *stream, scan_index **out);
 
 /* Shape parameters of the intersection kernels (Algorithm 1's per-edge
  * intersections). Every setting gives the same index bit for bit; they only

@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscan.so")
 
 SCAN_OK, SCAN_EINVAL, SCAN_EGRAPH, SCAN_ENOMEM, SCAN_EDEVICE, SCAN_EBUSY = 0, -1, -2, -3, -4, -5
-COSINE, JACCARD = 0, 1
+COSINE, JACCARD, WEIGHTED_COSINE = 0, 1, 2
 SCAN_VALIDATE, SCAN_KEEP_SIMS, SCAN_KEEP_COUNTS, SCAN_PROFILE = 1, 2, 4, 8
 SCAN_TUNE_SEARCH_WINDOWS = 1
 (ARR_OFFSETS, ARR_NO_IDS, ARR_NO_SIM, ARR_CO_OFF, ARR_CO_IDS, ARR_CO_THR, ARR_SIMS,
@@ -75,7 +75,7 @@ _RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_
 
 # Every symbol include/scan.h declares (checked by the CPU tests).
 EXPORTS = [
-    "scan_set_allocator", "scan_build_index", "scan_build_index_batch", "scan_query",
+    "scan_set_allocator", "scan_build_index", "scan_build_index_batch", "scan_build_index_weighted", "scan_query",
     "scan_query_ex", "scan_query_batch", "scan_index_get_info", "scan_index_export",
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "scan_set_allocator": ([_ALLOC_FN, _RELEASE_FN, vp], i32),
         "scan_build_index": ([P(_Csr), i32, u32, vp, P(vp)], i32),
         "scan_build_index_batch": ([P(_Csr), i32, i32, u32, vp, P(vp)], i32),
+        "scan_build_index_weighted": ([P(_Csr), vp, u32, vp, P(vp)], i32),
         "scan_build_index_ex": ([P(_Csr), i32, i32, u32, P(_Tune), vp, P(vp)], i32),
         "scan_autotune": ([P(_Csr), i32, i32, i32, vp, P(_Tune), P(ctypes.c_float)], i32),
         "scan_segmented_sort": ([vp, i64, vp, vp, vp, vp], i32),
@@ -292,6 +293,31 @@ def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None, 
     out = ctypes.c_void_p()
     _check(lib.scan_build_index(ctypes.byref(c), int(kind), int(flags), ctypes.c_void_p(s), ctypes.byref(out)))
     del keep
+    return Index(out.value, s)
+
+
+def scan_build_index_weighted(off, adj, weights, flags: int = 0, stream=None) -> Index:
+    """Builds the index under Section 3.1's weighted cosine; weights (float64,
+    one per CSR slot, parallel to adj) live where the graph does: a GPU
+    tensor with GPU tensors, a numpy array with numpy arrays."""
+    lib = _ready()
+    c, keep = _csr_struct(off, adj)
+    if c.on_device:
+        import torch
+        if not (isinstance(weights, torch.Tensor) and weights.is_cuda and weights.dtype == torch.float64):
+            raise TypeError("weights must be a float64 GPU tensor when the graph is on the GPU")
+        weights = weights.contiguous()
+        ptr = weights.data_ptr() if weights.numel() else None
+    else:
+        weights = np.ascontiguousarray(weights, dtype=np.float64)
+        ptr = weights.ctypes.data if weights.size else None
+    if (weights.numel() if hasattr(weights, "numel") else weights.size) != c.nnz:
+        raise ValueError(f"weights must have nnz = {c.nnz} entries")
+    s = _stream_handle(stream)
+    out = ctypes.c_void_p()
+    _check(lib.scan_build_index_weighted(ctypes.byref(c), ctypes.c_void_p(ptr), int(flags), ctypes.c_void_p(s),
+                                         ctypes.byref(out)))
+    del keep, weights
     return Index(out.value, s)
 
 

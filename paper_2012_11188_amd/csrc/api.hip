@@ -214,6 +214,16 @@ scan_status scan_build_index(const scan_csr *g, scan_sim_kind kind, uint32_t fla
   return build_index(g, (int32_t)kind, flags, (hipStream_t)stream, default_config(), out);
 }
 
+scan_status scan_build_index_weighted(const scan_csr *g, const double *weights, uint32_t flags,
+                                      void *stream, scan_index **out) {
+  if (!out) return fail(SCAN_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!g) return fail(SCAN_EINVAL, "null graph");
+  if (!weights && g->nnz > 0) return fail(SCAN_EINVAL, "null weights");
+  return build_index_batch(g, 1, SCAN_SIM_WEIGHTED_COSINE, flags, (hipStream_t)stream, default_config(), out,
+                           weights);
+}
+
 scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_kind kind,
                                    uint32_t flags, void *stream, scan_index **outs) {
   return build_index_batch(gs, count, (int32_t)kind, flags, (hipStream_t)stream, default_config(),

@@ -486,13 +486,20 @@ class HostPack {
 }  // namespace
 
 scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint32_t flags,
-                              hipStream_t s, const IntersectConfig &cfg, scan_index **outs) {
+                              hipStream_t s, const IntersectConfig &cfg, scan_index **outs,
+                              const double *weights) {
   if (G < 0 || (G > 0 && (!gs || !outs))) return fail(SCAN_EINVAL, "bad batch arguments");
   for (int32_t g = 0; g < G; ++g) {
     outs[g] = nullptr;
     SCAN_TRY(check_csr(&gs[g]));
   }
-  if (kind != SCAN_SIM_COSINE && kind != SCAN_SIM_JACCARD) return fail(SCAN_EINVAL, "unknown similarity kind %d", kind);
+  const bool weighted = kind == SCAN_SIM_WEIGHTED_COSINE;
+  if (kind != SCAN_SIM_COSINE && kind != SCAN_SIM_JACCARD && !weighted)
+    return fail(SCAN_EINVAL, "unknown similarity kind %d", kind);
+  if (weighted && (G != 1 || (!weights && G > 0 && gs[0].nnz > 0)))
+    return fail(SCAN_EINVAL, "the weighted cosine takes one graph and its edge weights (scan_build_index_weighted)");
+  if (!weighted && weights) return fail(SCAN_EINVAL, "edge weights given for an unweighted similarity");
+  if (weighted && (flags & SCAN_KEEP_COUNTS)) return fail(SCAN_EINVAL, "the weighted cosine has no intersection counts");
   if (flags & ~(uint32_t)(SCAN_VALIDATE | SCAN_KEEP_SIMS | SCAN_KEEP_COUNTS | SCAN_PROFILE)) return fail(SCAN_EINVAL, "unknown build flags 0x%x", flags);
   if (cfg.small_max < 1 || cfg.small_max > 4096 || cfg.spc < 1 || cfg.spc > 1024 || cfg.wbits < 10 || cfg.wbits > 24)
     return fail(SCAN_EINVAL, "bad intersection config");
@@ -612,6 +619,16 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       if (herr[2 * g])
         return fail(SCAN_EGRAPH, "graph %d is not a simple undirected CSR with ascending rows (first bad row %d)", g, herr[2 * g + 1]);
   }
+  const double *w_dev = weights;  // edge weights on the device (weighted cosine)
+  if (weighted && NNZ > 0) {
+    if (!gs[0].on_device) {
+      double *dw;
+      SCAN_TRY(tmp.alloc(&dw, NNZ));
+      SCAN_HIP_TRY(hipMemcpyAsync(dw, weights, (size_t)NNZ * 8, hipMemcpyHostToDevice, s));
+      w_dev = dw;
+    }
+    if (flags & SCAN_VALIDATE) SCAN_TRY(check_weights(w_dev, NNZ, tmp, s));
+  }
   // Index arrays (their sizes do not depend on the degrees): allocated while
   // the device runs the kernels above.
   int32_t *no_ids, *co_ids, *counts = nullptr;
@@ -674,7 +691,11 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       ist.ev_end = prof->ev[3];
       ist.host_counts = prof->plan_counts;
     }
-    SCAN_TRY(intersect_all(cfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
+    if (weighted)
+      SCAN_TRY(weighted_similarity_all(N, NNZ, off_u, deg, adj_u, w_dev, sims, tmp, s, ist.ev_start, ist.ev_mid,
+                                       ist.ev_end));
+    else
+      SCAN_TRY(intersect_all(cfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
     if (prof) {
       prof->window_bits = ist.wbits;
       prof->intersect_launches = ist.launches;

@@ -35,6 +35,14 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
                           const int32_t *deg, const int32_t *adj, int kind, double *sims,
                           int32_t *counts, int device, hipStream_t s, IntersectStats *stats);
 
+// Weighted cosine of every edge into both CSR slots of sims (weighted.hip);
+// events (may be null) before the square sums, before the products, after.
+scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, const int32_t *deg,
+                                    const int32_t *adj, const double *w, double *sims, DevArena &tmp,
+                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end);
+// SCAN_EGRAPH unless every weight is finite (waits for the stream).
+scan_status check_weights(const double *w, int64_t nnz, DevArena &tmp, hipStream_t s);
+
 // Per-query device workspace (one slot of a batch).
 struct QuerySlot {
   int32_t *parent = nullptr;  // int32[n] union-find parents (read for cores only)
@@ -121,8 +129,11 @@ void index_release(scan_index *ix);
 
 scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStream_t stream,
                         const IntersectConfig &cfg, scan_index **out);
+// weights: per-slot edge weights (kind SCAN_SIM_WEIGHTED_COSINE, one graph
+// only), on the same side (host or device) as the graph.
 scan_status build_index_batch(const scan_csr *gs, int32_t count, int32_t kind, uint32_t flags,
-                              hipStream_t stream, const IntersectConfig &cfg, scan_index **outs);
+                              hipStream_t stream, const IntersectConfig &cfg, scan_index **outs,
+                              const double *weights = nullptr);
 
 // Runs `count` queries. mu/eps host arrays; memberships[i] / is_core[i] are
 // device pointers (is_core may hold nulls). Slots are workspaces, one per
