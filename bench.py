@@ -301,6 +301,41 @@ def roles_timing(scan, torch, ix, g, count=20):
             "outliers": outl, "bytes_bound": nbytes, "gbs_bound": nbytes / (ms * 1e-3) / 1e9}}
 
 
+def weighted_timing(scan, torch, graphgen, g, off, adj, st, steps):
+    """Section 3.1's weighted cosine on the same graph, with seeded weights
+    uniform in [0.05, 1) (equal for both directions of an edge): builds timed
+    like the headline, the split between the square sums and the owner
+    products (hipEvents), the owner kernel's algorithmic bytes and a sampled
+    oracle rate. Owner kernel bytes: every lower row's ids and weights once
+    per owned edge (12 B per id) and one 4 B tile probe per id (16 W_min),
+    both similarity slots (16 B per edge) and the owner rows' ids and weights
+    (12 B per slot)."""
+    import oracle
+
+    wh = graphgen.edge_weights(g, 2020)
+    w = torch.from_numpy(wh).cuda()
+    ms, dev_ms, profs, _ = timed_builds(
+        scan, torch, lambda: [scan.scan_build_index_weighted(off, adj, w, scan.SCAN_PROFILE)], steps, 1)
+    phases = {k: med(profs, k) for k in PHASES}
+    owner_ms = phases["intersect_big_ms"]
+    nbytes = 16 * st["w_min"] + 16 * g.num_edges + 12 * g.nnz
+    k = 20_000
+    rng = np.random.default_rng(7)
+    slots = rng.integers(0, g.nnz, k)
+    u = np.searchsorted(g.off, slots, side="right") - 1
+    t = time.perf_counter()
+    oracle.weighted_edge_similarities(g, wh, u, g.adj[slots].astype(np.int64))
+    tc = time.perf_counter() - t
+    return {"value": g.num_edges / (ms * 1e-3), "unit": "edges/s", "ms_per_step": ms, "device_ms_per_step": dev_ms,
+            "phases_ms": phases, "weights": "uniform [0.05, 1), seed 2020, symmetric",
+            "square_sums_ms": phases["intersect_small_ms"], "k_w_owner": {
+                "bytes": nbytes, "launch_ms": owner_ms, "achieved_gbs": nbytes / max(owner_ms, 1e-6) / 1e6,
+                "frac": nbytes / max(owner_ms, 1e-6) / 1e6 / HBM_PEAK_GBS},
+            "cpu_baseline": {"value": k / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                             "sample": f"weighted similarity of {k} uniformly sampled edges, one thread, {tc:.1f} s "
+                                       f"(similarity phase only)"}}
+
+
 def sweep_timing(scan, torch, ix, dmax, batch=32):
     """Section 7.3.4's parameter selection on the index: the modularity of
     every (mu, eps) of the paper's grid (mu = 2..2^18 in powers of two up to
@@ -374,6 +409,9 @@ def rmat_workload(args, scan, torch, graphgen):
         jms, jdev, jph, _ = results[scan.JACCARD]
         extra["jaccard"] = {"value": g.num_edges / (jms * 1e-3), "ms_per_step": jms, "device_ms_per_step": jdev,
                             "phases_ms": jph}
+    if scale == 20 and not args.no_weighted:
+        extra["weighted"] = weighted_timing(scan, torch, graphgen, g, off, adj, st, args.steps)
+        log(f"weighted: {extra['weighted']}")
     if scale == 20 and not args.no_queries:
         extra["query"] = closed_loop_queries(scan, torch, ix, g.n, args.queries, args.query_batch)
         log(f"queries: {extra['query']}")
@@ -473,6 +511,7 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-queries", action="store_true")
+    ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-cosine build timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

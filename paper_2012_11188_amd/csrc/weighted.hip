@@ -34,8 +34,8 @@ namespace {
 constexpr int kWUnit = 128;                  // CSR slots per workgroup
 constexpr int kWThreads = 256;
 constexpr int kWWaves = kWThreads / kWave;
-constexpr int kWTile = 2048;                 // owner ids (and weights) per LDS tile
-constexpr int kWRows = kWThreads;            // row offsets staged at a time
+constexpr int kWTile = 1024;                 // owner ids (and weights) per LDS tile
+constexpr int kWRows = 64;                   // row offsets staged at a time
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -52,6 +52,9 @@ __device__ __forceinline__ double lane_f64(double v, int k) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Lanes past the end of a row re-read its last slot (clamped, so the id and
+// weight loads need no branch and are issued together) and contribute +0.0,
+// which leaves a non-negative running sum unchanged.
 __global__ __launch_bounds__(256) void k_w_square_sums(const int64_t *off, const int32_t *adj, const double *w,
                                                        int64_t n, double *S) {
   const int lane = lane_id();
@@ -60,21 +63,32 @@ __global__ __launch_bounds__(256) void k_w_square_sums(const int64_t *off, const
     const int64_t o = uniform64(off[v]), d = uniform64(off[v + 1]) - o;
     double acc = 0.0;
     bool self = false;
-    for (int64_t c = 0; c < d; c += kWave) {
+    int32_t xr = 0;  // raw loads of the chunk in flight (masked where used)
+    double wr = 0.0;
+    auto fetch = [&](int64_t c) {
       const int64_t p = c + lane;
-      const bool in = p < d;
-      const int32_t x = in ? adj[o + p] : INT_MAX;
-      const double wx = in ? w[o + p] : 0.0;
+      const int64_t q = o + (p < d ? p : d - 1);
+      xr = adj[q];
+      wr = w[q];
+    };
+    if (d > 0) fetch(0);
+    for (int64_t c = 0; c < d; c += kWave) {
+      const bool in = c + lane < d;
+      const double wx = in ? wr : 0.0;
       const double sq = wx * wx;
-      const int m = (int)(d - c < kWave ? d - c : kWave);
-      const uint64_t above = __ballot(in && x > v);
-      const int first_above = above ? __ffsll((unsigned long long)above) - 1 : kWave;
-      for (int k = 0; k < m; ++k) {
-        if (!self && k == first_above) {
-          acc += 1.0;
-          self = true;
+      const uint64_t above = __ballot(in && xr > v);
+      if (c + kWave < d) fetch(c + kWave);  // the next chunk's loads overlap this chunk's sum
+      if (!self && above) {                 // the self term 1 goes before the first id above v
+        const int fa = __ffsll((unsigned long long)above) - 1;
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) {
+          if (k == fa) acc += 1.0;
+          acc += lane_f64(sq, k);
         }
-        acc += lane_f64(sq, k);
+        self = true;
+      } else {
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) acc += lane_f64(sq, k);
       }
     }
     if (!self) acc += 1.0;
@@ -181,8 +195,11 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
           while (c < du) {
             const int32_t p = c + lane;
             const bool in = p < du;
-            const int32_t x = in ? adj[ou + p] : INT_MAX;
-            const double wl = in ? w[ou + p] : 0.0;
+            const int64_t q = ou + (in ? p : du - 1);  // clamped: both loads issue together
+            const int32_t xq = adj[q];
+            const double wq = w[q];
+            const int32_t x = in ? xq : INT_MAX;
+            const double wl = in ? wq : 0.0;
             const bool valid = in && (last || x <= hi);
             // lower_bound of x in the tile
             int32_t lo = 0, len = tn;
