@@ -64,6 +64,10 @@ def _load():
     lib.gg_draw.restype = ctypes.c_uint64
     lib.gg_unit.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.gg_unit.restype = ctypes.c_double
+    lib.gg_gaussians.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p]
+    lib.gg_gaussians.restype = None
+    lib.gg_permutation.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p]
+    lib.gg_permutation.restype = None
     lib.gg_edge_weights.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
     lib.gg_edge_weights.restype = None
@@ -160,6 +164,23 @@ def edge_weights(g: Graph, seed: int, lo: float = 0.05, hi: float = 1.0) -> np.n
     if g.nnz:
         lib.gg_edge_weights(g.n, off.ctypes.data, adj.ctypes.data, seed, lo, hi, w.ctypes.data)
     return w
+
+
+def gaussians(n: int, k: int, seed: int) -> np.ndarray:
+    """float64[n, k] standard normal draws (Box-Muller over the stream): the
+    random hyperplanes of SimHash, one coordinate per vertex and sample."""
+    out = np.zeros((n, k), np.float64)
+    if n and k:
+        _load().gg_gaussians(n, k, seed, out.ctypes.data)
+    return out
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    """uint32[n], a uniformly random permutation of 0..n-1 (Fisher-Yates)."""
+    out = np.zeros(n, np.uint32)
+    if n:
+        _load().gg_permutation(n, seed, out.ctypes.data)
+    return out
 
 
 def degree_stats(g: Graph) -> dict:

@@ -60,6 +60,26 @@ typedef struct {
 
 uint64_t gg_draw(uint64_t seed, uint64_t ctr) { return draw(seed, ctr); }
 
+// Standard normal draws g[x * k + i] (x < n, i < k) by the Box-Muller
+// transform of two uniforms of the stream: u1 = 1 - unit(seed, 2c) is in
+// (0, 1], u2 = unit(seed, 2c + 1), g = sqrt(-2 ln u1) cos(2 pi u2), c = x * k + i.
+void gg_gaussians(int64_t n, int64_t k, uint64_t seed, double *g) {
+  const double two_pi = 6.283185307179586;
+  for (int64_t c = 0; c < n * k; ++c) {
+    const double u1 = 1.0 - unit(seed, 2 * (uint64_t)c), u2 = unit(seed, 2 * (uint64_t)c + 1);
+    g[c] = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2);
+  }
+}
+
+// A uniformly random permutation of 0..n-1 (Fisher-Yates with the stream).
+void gg_permutation(int64_t n, uint64_t seed, uint32_t *p) {
+  for (int64_t i = 0; i < n; ++i) p[i] = (uint32_t)i;
+  for (int64_t i = n - 1; i > 0; --i) {
+    const int64_t j = (int64_t)(draw(seed, (uint64_t)i) % (uint64_t)(i + 1));
+    std::swap(p[i], p[j]);
+  }
+}
+
 // Edge weights parallel to adj, the same for both directions of an edge:
 // w = lo + (hi - lo) * unit(seed, min(u, v) * n + max(u, v)).
 void gg_edge_weights(int64_t n, const int64_t *off, const int32_t *adj, uint64_t seed, double lo,

@@ -74,6 +74,12 @@ def _load():
     lib.oracle_weighted_edge_similarity.restype = f64
     lib.oracle_weighted_square_sum.argtypes = [vp, vp, vp, i64]
     lib.oracle_weighted_square_sum.restype = f64
+    lib.oracle_simhash_sketches.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
+    lib.oracle_simhash_sketches.restype = None
+    lib.oracle_minhash_sketches.argtypes = [i64, vp, vp, i64, vp, i64, vp, vp]
+    lib.oracle_minhash_sketches.restype = None
+    lib.oracle_lsh_similarities.argtypes = [i64, vp, vp, vp, i32, i64, vp, vp, i32, vp]
+    lib.oracle_lsh_similarities.restype = None
     _lib = lib
     return lib
 
@@ -228,6 +234,56 @@ def build_index_weighted(g, w: np.ndarray, threads: int = 1) -> OracleIndex:
     co_off, co_ids, co_thr = core_order(g, no_sim, dmax, threads)
     return OracleIndex(g.n, off, dmax, WEIGHTED_COSINE, np.zeros(g.nnz, np.int32), sim, no_ids, no_sim,
                        co_off, co_ids, co_thr)
+
+
+def simhash_sketches(g, k: int, gauss: np.ndarray, vs, w: np.ndarray | None = None) -> np.ndarray:
+    """uint8[len(vs), k] SimHash bits (Section 2.1.2) of N[v] for v in vs."""
+    off, adj = _csr(g)
+    gauss = np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1)
+    assert gauss.size == g.n * k
+    vs = np.ascontiguousarray(vs, dtype=np.int64)
+    out = np.zeros((len(vs), k), np.uint8)
+    ww = None if w is None else _weights(g, w)
+    _load().oracle_simhash_sketches(_p(off), _p(adj), None if ww is None else _p(ww), k, _p(gauss), len(vs),
+                                    _p(vs), _p(out))
+    return out
+
+
+def minhash_sketches(g, k: int, perm: np.ndarray, vs) -> np.ndarray:
+    """uint32[len(vs), k] k-partition MinHash sketches of N[v] (empty bin = 2^32-1)."""
+    off, adj = _csr(g)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    vs = np.ascontiguousarray(vs, dtype=np.int64)
+    out = np.zeros((len(vs), k), np.uint32)
+    _load().oracle_minhash_sketches(g.n, _p(off), _p(adj), k, _p(perm), len(vs), _p(vs), _p(out))
+    return out
+
+
+def lsh_similarities(g, kind: int, k: int, gauss=None, perm=None, w=None, threads: int = 1) -> np.ndarray:
+    """Per-slot approximate similarities (Section 5 + the Section 6.3 heuristic):
+    kind COSINE uses SimHash with `gauss` (n x k), weighted when w is given;
+    kind JACCARD uses k-partition MinHash with `perm`."""
+    off, adj = _csr(g)
+    sim = np.zeros(g.nnz, np.float64)
+    gp = None if gauss is None else np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1)
+    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
+    ww = None if w is None else _weights(g, w)
+    _load().oracle_lsh_similarities(g.n, _p(off), _p(adj), None if ww is None else _p(ww), kind, k,
+                                    None if gp is None else _p(gp), None if pp is None else _p(pp), threads,
+                                    _p(sim))
+    return sim
+
+
+def build_index_lsh(g, kind: int, k: int, gauss=None, perm=None, w=None, threads: int = 1) -> OracleIndex:
+    """Approximate index: LSH similarities, then Algorithm 2's orders."""
+    off, _ = _csr(g)
+    dmax = int(_load().oracle_max_degree(g.n, _p(off)))
+    sim = lsh_similarities(g, kind, k, gauss, perm, w, threads)
+    no_ids, no_sim = neighbor_order(g, sim, threads)
+    co_off, co_ids, co_thr = core_order(g, no_sim, dmax, threads)
+    okind = WEIGHTED_COSINE if (kind == COSINE and w is not None) else kind
+    return OracleIndex(g.n, off, dmax, okind, np.zeros(g.nnz, np.int32), sim, no_ids, no_sim, co_off, co_ids,
+                       co_thr)
 
 
 def query(ix: OracleIndex, mu: int, eps: float):

@@ -17,7 +17,13 @@
 //   * hubs and outliers among the unclustered vertices: Section 4.3;
 //   * weighted cosine (Section 3.1): w(x, x) = 1, closed-neighbourhood sums
 //     taken term by term in ascending vertex id, similarity =
-//     dot / sqrt(S_u * S_v) with S the sums of squared weights.
+//     dot / sqrt(S_u * S_v) with S the sums of squared weights;
+//   * approximate similarities (Section 5; heuristic of Section 6.3): SimHash
+//     bits are signs (>= 0 -> 1) of ascending-x dot products with the given
+//     Gaussian draws, estimate cos(pi h / k); k-partition MinHash with the
+//     given permutation, estimate matches / (k - bins empty in both); only
+//     edges between two vertices of degree > k (cosine) or > 3k/2 (Jaccard)
+//     are approximated, the rest are exact.
 //
 // Readings where the paper leaves a choice (each also listed in the design
 // notes):
@@ -155,6 +161,63 @@ double weighted_cosine(const int64_t *off, const int32_t *adj, const double *w, 
   return closed_weighted_dot(ru, rv) / std::sqrt(closed_square_sum(ru) * closed_square_sum(rv));
 }
 
+// Approximate similarities (Section 5, with the degree heuristic of Section
+// 6.3). The random draws are inputs: gauss[x * k + i] is coordinate x of the
+// i-th SimHash direction, perm is the one permutation of k-partition MinHash.
+//
+// SimHash sketch of v: bit i is 1 iff the dot product of N[v] (weights
+// w(v, x), w(v, v) = 1; all 1 without weights) with direction i is >= 0, the
+// dot product summed term by term in ascending x.
+std::vector<uint8_t> simhash_sketch(const int64_t *off, const int32_t *adj, const double *w, int64_t k,
+                                    const double *gauss, int64_t v) {
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t s = off[v]; s < off[v + 1]; ++s) row.push_back({adj[s], w ? w[s] : 1.0});
+  row.push_back({(int32_t)v, 1.0});
+  std::sort(row.begin(), row.end());
+  std::vector<uint8_t> bits(k);
+  for (int64_t i = 0; i < k; ++i) {
+    double dot = 0.0;
+    for (const auto &e : row) dot += e.second * gauss[(int64_t)e.first * k + i];
+    bits[i] = dot >= 0.0 ? 1 : 0;
+  }
+  return bits;
+}
+
+// k-partition (one permutation) MinHash sketch of v: the permuted range
+// [0, n) is cut into k equal bins, bin(x) = floor(perm[x] * k / n); entry b
+// is the least perm[x] over x in N[v] with bin(x) = b, or 0xffffffff if none.
+std::vector<uint32_t> minhash_sketch(const int64_t *off, const int32_t *adj, int64_t n, int64_t k,
+                                     const uint32_t *perm, int64_t v) {
+  std::vector<uint32_t> sk(k, 0xffffffffu);
+  auto take = [&](int64_t x) {
+    const uint32_t p = perm[x];
+    const int64_t b = (int64_t)((uint64_t)p * (uint64_t)k / (uint64_t)n);
+    sk[b] = std::min(sk[b], p);
+  };
+  take(v);
+  for (int64_t s = off[v]; s < off[v + 1]; ++s) take(adj[s]);
+  return sk;
+}
+
+// cos(pi h / k) for h differing SimHash bits: the angle estimate of Section 2.1.2.
+double simhash_estimate(int64_t h, int64_t k) { return std::cos(M_PI * (double)h / (double)k); }
+
+// Matching non-empty bins over the bins not empty in both sketches (the
+// one-permutation estimator of the Jaccard similarity).
+double minhash_estimate(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
+  int64_t match = 0, empty = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    if (a[i] == 0xffffffffu && b[i] == 0xffffffffu) ++empty;
+    else if (a[i] == b[i]) ++match;
+  }
+  return (double)match / (double)((int64_t)a.size() - empty);
+}
+
+// Section 6.3's heuristic: a vertex is high degree when its degree exceeds k
+// (cosine) or 3k/2 (Jaccard); only edges between two such vertices are
+// approximated.
+bool lsh_high(int32_t kind, int64_t deg, int64_t k) { return kind == 0 ? deg > k : 2 * deg > 3 * k; }
+
 // Sort key for both orders: similarity descending, then vertex id ascending.
 struct Entry {
   double key;
@@ -247,6 +310,62 @@ double oracle_weighted_edge_similarity(const int64_t *off, const int32_t *adj, c
 // Sum of w(v, x)^2 over N[v] (the square of Algorithm 1's norm of v).
 double oracle_weighted_square_sum(const int64_t *off, const int32_t *adj, const double *w, int64_t v) {
   return closed_square_sum(closed_row(off, adj, w, v));
+}
+
+// SimHash sketches of the given vertices: bits[j * k + i] for vertex vs[j].
+void oracle_simhash_sketches(const int64_t *off, const int32_t *adj, const double *w, int64_t k,
+                             const double *gauss, int64_t count, const int64_t *vs, uint8_t *bits) {
+  for (int64_t j = 0; j < count; ++j) {
+    const auto b = simhash_sketch(off, adj, w, k, gauss, vs[j]);
+    std::copy(b.begin(), b.end(), bits + j * k);
+  }
+}
+
+// k-partition MinHash sketches of the given vertices: sk[j * k + b].
+void oracle_minhash_sketches(int64_t n, const int64_t *off, const int32_t *adj, int64_t k, const uint32_t *perm,
+                             int64_t count, const int64_t *vs, uint32_t *sk) {
+  for (int64_t j = 0; j < count; ++j) {
+    const auto a = minhash_sketch(off, adj, n, k, perm, vs[j]);
+    std::copy(a.begin(), a.end(), sk + j * k);
+  }
+}
+
+// Approximate similarities of every edge, both CSR slots: kind 0 SimHash
+// (cosine; weighted when w is not null), kind 1 k-partition MinHash
+// (Jaccard). Edges that are not between two high-degree vertices get the
+// exact similarity of the same kind.
+void oracle_lsh_similarities(int64_t n, const int64_t *off, const int32_t *adj, const double *w, int32_t kind,
+                             int64_t k, const double *gauss, const uint32_t *perm, int32_t threads, double *sim) {
+  std::vector<std::vector<uint8_t>> sbits(n);
+  std::vector<std::vector<uint32_t>> mh(n);
+  parallel_for_dynamic(n, threads, [&](int64_t v) {
+    if (!lsh_high(kind, degree(off, v), k)) return;
+    if (kind == 0) sbits[v] = simhash_sketch(off, adj, w, k, gauss, v);
+    else mh[v] = minhash_sketch(off, adj, n, k, perm, v);
+  });
+  parallel_for_dynamic(n, threads, [&](int64_t u) {
+    for (int64_t s = off[u]; s < off[u + 1]; ++s) {
+      int64_t v = adj[s];
+      if (v < u) continue;
+      double x;
+      if (lsh_high(kind, degree(off, u), k) && lsh_high(kind, degree(off, v), k)) {
+        if (kind == 0) {
+          int64_t h = 0;
+          for (int64_t i = 0; i < k; ++i) h += sbits[u][i] != sbits[v][i];
+          x = simhash_estimate(h, k);
+        } else {
+          x = minhash_estimate(mh[u], mh[v]);
+        }
+      } else if (kind == 0 && w) {
+        x = weighted_cosine(off, adj, w, u, v);
+      } else {
+        x = similarity(kind, common_open_neighbours(off, adj, u, v) + 2, degree(off, u) + 1, degree(off, v) + 1);
+      }
+      int64_t m = std::lower_bound(adj + off[v], adj + off[v + 1], (int32_t)u) - adj;
+      sim[s] = x;
+      sim[m] = x;
+    }
+  });
 }
 
 // Algorithm 2, MakeNeighborOrder: each row sorted by non-increasing
