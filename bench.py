@@ -336,6 +336,33 @@ def weighted_timing(scan, torch, graphgen, g, off, adj, st, steps):
                                        f"(similarity phase only)"}}
 
 
+def lsh_timing(scan, torch, graphgen, g, off, adj, exact_ms, steps, k=256):
+    """Section 5's approximate index on the same graph with k = 256 samples:
+    SimHash (cosine; seeded Gaussian draws, n x k) and k-partition MinHash
+    (Jaccard; a seeded permutation), edges between two vertices of degree > k
+    (> 3k/2 for Jaccard) approximated, the rest exact. Builds timed like the
+    headline; the draws are resident before timing."""
+    deg = np.diff(g.off)
+    rows = np.repeat(np.arange(g.n), deg)
+    out = {"samples": k}
+    for name, kind in (("simhash_cosine", scan.COSINE), ("minhash_jaccard", scan.JACCARD)):
+        if kind == scan.COSINE:
+            gauss, perm = torch.from_numpy(graphgen.gaussians(g.n, k, 256)).cuda(), None
+            hi = deg > k
+        else:
+            gauss, perm = None, torch.from_numpy(graphgen.permutation(g.n, 256)).cuda()
+            hi = 2 * deg > 3 * k
+        ms, dev_ms, profs, _ = timed_builds(
+            scan, torch, lambda: [scan.scan_build_index_lsh(off, adj, kind, k, gauss, perm, None, scan.SCAN_PROFILE)],
+            steps, 1)
+        out[name] = {"value": g.num_edges / (ms * 1e-3), "unit": "edges/s", "ms_per_step": ms,
+                     "device_ms_per_step": dev_ms, "phases_ms": {k_: med(profs, k_) for k_ in PHASES},
+                     "approximated_slots": int((hi[rows] & hi[g.adj]).sum()), "sketched_vertices": int(hi.sum()),
+                     "over_exact_ms": ms - exact_ms}
+        del gauss, perm
+    return out
+
+
 def sweep_timing(scan, torch, ix, dmax, batch=32):
     """Section 7.3.4's parameter selection on the index: the modularity of
     every (mu, eps) of the paper's grid (mu = 2..2^18 in powers of two up to
@@ -409,6 +436,9 @@ def rmat_workload(args, scan, torch, graphgen):
         jms, jdev, jph, _ = results[scan.JACCARD]
         extra["jaccard"] = {"value": g.num_edges / (jms * 1e-3), "ms_per_step": jms, "device_ms_per_step": jdev,
                             "phases_ms": jph}
+    if scale == 20 and not args.no_lsh:
+        extra["lsh"] = lsh_timing(scan, torch, graphgen, g, off, adj, ms, args.steps)
+        log(f"lsh: {extra['lsh']}")
     if scale == 20 and not args.no_weighted:
         extra["weighted"] = weighted_timing(scan, torch, graphgen, g, off, adj, st, args.steps)
         log(f"weighted: {extra['weighted']}")
@@ -512,6 +542,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-queries", action="store_true")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-cosine build timing")
+    ap.add_argument("--no-lsh", action="store_true", help="skip the approximate (LSH) build timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -181,6 +181,40 @@ scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_k
 scan_status scan_build_index_weighted(const scan_csr *g, const double *weights, uint32_t flags,
                                       void *stream, scan_index **out);
 
+/* Approximate index (Section 5; the degree heuristic of Section 6.3): the
+ * edges between two high-degree vertices (degree > samples for the cosine
+ * kinds, > 3 * samples / 2 for Jaccard) get LSH estimates, every other edge
+ * its exact similarity; the orders and queries are built on those values.
+ *   SCAN_SIM_COSINE / SCAN_SIM_WEIGHTED_COSINE: SimHash. Bit i of v's sketch
+ *     is 1 iff sum over x in N[v] (ascending x) of w(v, x) * gauss[x * k + i]
+ *     is >= 0 (w(v, v) = 1; all weights 1 for SCAN_SIM_COSINE); the estimate
+ *     is cos(pi * h / k) for h differing bits of the two sketches.
+ *   SCAN_SIM_JACCARD: k-partition MinHash with one permutation: bin(x) =
+ *     floor(perm[x] * k / n), entry b of v's sketch the least perm[x] over x
+ *     in N[v] in bin b; the estimate is matching non-empty entries / (k -
+ *     entries empty in both).
+ * The random draws are caller inputs (host or device, like the graph):
+ * gauss holds n * samples standard normal values, perm a permutation of
+ * 0..n-1 (values >= n are rejected). */
+typedef struct {
+  int32_t samples;          /* k: a multiple of 64 in [64, 4096]              */
+  int32_t reserved;         /* 0                                              */
+  const double *gauss;      /* SimHash draws, row-major [x * samples + i]     */
+  const uint32_t *perm;     /* MinHash permutation                            */
+  const double *weights;    /* SCAN_SIM_WEIGHTED_COSINE: edge weights as for
+                               scan_build_index_weighted; otherwise NULL     */
+} scan_lsh;
+
+/* Builds the approximate index of graph g. kind: SCAN_SIM_COSINE or
+ * SCAN_SIM_WEIGHTED_COSINE (SimHash, needs gauss) or SCAN_SIM_JACCARD
+ * (MinHash, needs perm). The inputs must stay valid until the stream reaches
+ * the end of the build. Errors: as scan_build_index, plus SCAN_EINVAL for a
+ * null lsh, samples out of range, a missing draw array, weights with another
+ * kind or none with SCAN_SIM_WEIGHTED_COSINE, SCAN_KEEP_COUNTS, or a
+ * permutation value >= n. */
+scan_status scan_build_index_lsh(const scan_csr *g, scan_sim_kind kind, const scan_lsh *lsh, uint32_t flags,
+                                 void *stream, scan_index **out);
+
 /* Shape parameters of the intersection kernels (Algorithm 1's per-edge
  * intersections). Every setting gives the same index bit for bit; they only
  * change speed. A zero field takes its default.
@@ -364,7 +398,8 @@ scan_status scan_similarity_values(scan_sim_kind kind, int64_t count, const int6
  * arrays. Segment i is [seg_off[i], seg_off[i+1]) (seg_off[0] = 0, non-
  * decreasing); each is sorted by key descending, ties by id ascending (the
  * order of Algorithm 2's rows and segments), into keys_out / ids_out.
- * Keys must be positive finite doubles, ids in [0, INT32_MAX). Synchronous,
+ * Keys must be finite doubles other than -0 (negative keys order below
+ * positive ones), ids in [0, INT32_MAX). Synchronous,
  * on the default stream. Errors: SCAN_EINVAL, SCAN_ENOMEM, SCAN_EDEVICE. */
 scan_status scan_segmented_sort(const int64_t *seg_off, int64_t nseg, const double *keys,
                                 const int32_t *ids, double *keys_out, int32_t *ids_out);

@@ -80,6 +80,8 @@ def _load():
     lib.oracle_minhash_sketches.restype = None
     lib.oracle_lsh_similarities.argtypes = [i64, vp, vp, vp, i32, i64, vp, vp, i32, vp]
     lib.oracle_lsh_similarities.restype = None
+    lib.oracle_lsh_edge_similarity.argtypes = [i64, vp, vp, vp, i32, i64, vp, vp, i64, i64]
+    lib.oracle_lsh_edge_similarity.restype = f64
     _lib = lib
     return lib
 
@@ -272,6 +274,18 @@ def lsh_similarities(g, kind: int, k: int, gauss=None, perm=None, w=None, thread
                                     None if gp is None else _p(gp), None if pp is None else _p(pp), threads,
                                     _p(sim))
     return sim
+
+
+def lsh_edge_similarities(g, kind: int, k: int, us, vs, gauss=None, perm=None, w=None) -> np.ndarray:
+    """lsh_similarities at the given edges only (sampled checks)."""
+    off, adj = _csr(g)
+    gp = None if gauss is None else np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1)
+    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
+    ww = None if w is None else _weights(g, w)
+    lib = _load()
+    args = (g.n, _p(off), _p(adj), None if ww is None else _p(ww), kind, k, None if gp is None else _p(gp),
+            None if pp is None else _p(pp))
+    return np.array([lib.oracle_lsh_edge_similarity(*args, int(u), int(v)) for u, v in zip(us, vs)], np.float64)
 
 
 def build_index_lsh(g, kind: int, k: int, gauss=None, perm=None, w=None, threads: int = 1) -> OracleIndex:

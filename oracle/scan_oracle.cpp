@@ -368,6 +368,22 @@ void oracle_lsh_similarities(int64_t n, const int64_t *off, const int32_t *adj, 
   });
 }
 
+// One edge of oracle_lsh_similarities, for sampled checks on large graphs.
+double oracle_lsh_edge_similarity(int64_t n, const int64_t *off, const int32_t *adj, const double *w, int32_t kind,
+                                  int64_t k, const double *gauss, const uint32_t *perm, int64_t u, int64_t v) {
+  if (lsh_high(kind, degree(off, u), k) && lsh_high(kind, degree(off, v), k)) {
+    if (kind == 0) {
+      const auto a = simhash_sketch(off, adj, w, k, gauss, u), b = simhash_sketch(off, adj, w, k, gauss, v);
+      int64_t h = 0;
+      for (int64_t i = 0; i < k; ++i) h += a[i] != b[i];
+      return simhash_estimate(h, k);
+    }
+    return minhash_estimate(minhash_sketch(off, adj, n, k, perm, u), minhash_sketch(off, adj, n, k, perm, v));
+  }
+  if (kind == 0 && w) return weighted_cosine(off, adj, w, u, v);
+  return similarity(kind, common_open_neighbours(off, adj, u, v) + 2, degree(off, u) + 1, degree(off, v) + 1);
+}
+
 // Algorithm 2, MakeNeighborOrder: each row sorted by non-increasing
 // similarity, ties by lower id.
 // One row: ids[0..d) with their similarities sim[0..d) -> sorted copy.

@@ -47,6 +47,11 @@ class _Csr(ctypes.Structure):
                 ("on_device", ctypes.c_int32), ("offsets", ctypes.c_void_p), ("adj", ctypes.c_void_p)]
 
 
+class _Lsh(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("reserved", ctypes.c_int32), ("gauss", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("dmax", ctypes.c_int64),
                 ("kind", ctypes.c_int32), ("flags", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
@@ -75,7 +80,8 @@ _RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_
 
 # Every symbol include/scan.h declares (checked by the CPU tests).
 EXPORTS = [
-    "scan_set_allocator", "scan_build_index", "scan_build_index_batch", "scan_build_index_weighted", "scan_query",
+    "scan_set_allocator", "scan_build_index", "scan_build_index_batch", "scan_build_index_weighted",
+    "scan_build_index_lsh", "scan_query",
     "scan_query_ex", "scan_query_batch", "scan_index_get_info", "scan_index_export",
     "scan_index_device_ptr", "scan_index_free", "scan_server_create", "scan_server_submit",
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
@@ -111,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "scan_build_index": ([P(_Csr), i32, u32, vp, P(vp)], i32),
         "scan_build_index_batch": ([P(_Csr), i32, i32, u32, vp, P(vp)], i32),
         "scan_build_index_weighted": ([P(_Csr), vp, u32, vp, P(vp)], i32),
+        "scan_build_index_lsh": ([P(_Csr), i32, P(_Lsh), u32, vp, P(vp)], i32),
         "scan_build_index_ex": ([P(_Csr), i32, i32, u32, P(_Tune), vp, P(vp)], i32),
         "scan_autotune": ([P(_Csr), i32, i32, i32, vp, P(_Tune), P(ctypes.c_float)], i32),
         "scan_segmented_sort": ([vp, i64, vp, vp, vp, vp], i32),
@@ -318,6 +325,40 @@ def scan_build_index_weighted(off, adj, weights, flags: int = 0, stream=None) ->
     _check(lib.scan_build_index_weighted(ctypes.byref(c), ctypes.c_void_p(ptr), int(flags), ctypes.c_void_p(s),
                                          ctypes.byref(out)))
     del keep, weights
+    return Index(out.value, s)
+
+
+def _side_ptr(a, on_device, dtype_np, dtype_name):
+    """Pointer of an optional input living where the graph lives."""
+    if a is None:
+        return None, None
+    if on_device:
+        import torch
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and str(a.dtype) == "torch." + dtype_name):
+            raise TypeError(f"{dtype_name} GPU tensor expected with a GPU graph")
+        a = a.contiguous()
+        return (a.data_ptr() if a.numel() else None), a
+    a = np.ascontiguousarray(a, dtype=dtype_np)
+    return (a.ctypes.data if a.size else None), a
+
+
+def scan_build_index_lsh(off, adj, kind: int, samples: int, gauss=None, perm=None, weights=None, flags: int = 0,
+                         stream=None) -> Index:
+    """Approximate index (Section 5 with Section 6.3's heuristic): SimHash for
+    COSINE / WEIGHTED_COSINE (gauss: n x samples float64 draws; weights for
+    the weighted kind), k-partition MinHash for JACCARD (perm: uint32
+    permutation of 0..n-1). Inputs live where the graph lives."""
+    lib = _ready()
+    c, keep = _csr_struct(off, adj)
+    pg, kg = _side_ptr(gauss, c.on_device, np.float64, "float64")
+    pp, kp = _side_ptr(perm, c.on_device, np.uint32, "uint32")
+    pw, kw = _side_ptr(weights, c.on_device, np.float64, "float64")
+    spec = _Lsh(int(samples), 0, pg, pp, pw)
+    s = _stream_handle(stream)
+    out = ctypes.c_void_p()
+    _check(lib.scan_build_index_lsh(ctypes.byref(c), int(kind), ctypes.byref(spec), int(flags), ctypes.c_void_p(s),
+                                    ctypes.byref(out)))
+    del keep, kg, kp, kw
     return Index(out.value, s)
 
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscan.so")
 SOURCES = ["api.hip", "build.hip", "intersect.hip", "segsort.hip", "query.hip", "server.hip", "quality.hip",
-           "weighted.hip"]
+           "weighted.hip", "lsh.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -O3, no fast-math, no FP contraction (the FP64 similarity must round like

@@ -224,6 +224,23 @@ scan_status scan_build_index_weighted(const scan_csr *g, const double *weights, 
                            weights);
 }
 
+scan_status scan_build_index_lsh(const scan_csr *g, scan_sim_kind kind, const scan_lsh *lsh, uint32_t flags,
+                                 void *stream, scan_index **out) {
+  if (!out) return fail(SCAN_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!g || !lsh) return fail(SCAN_EINVAL, "null graph or LSH description");
+  if (lsh->reserved) return fail(SCAN_EINVAL, "scan_lsh.reserved must be 0");
+  const bool weighted = kind == SCAN_SIM_WEIGHTED_COSINE;
+  if (weighted != (lsh->weights != nullptr) && g->nnz > 0)
+    return fail(SCAN_EINVAL, "edge weights go with SCAN_SIM_WEIGHTED_COSINE and only with it");
+  LshSpec spec;
+  spec.samples = lsh->samples;
+  spec.gauss = lsh->gauss;
+  spec.perm = lsh->perm;
+  return build_index_batch(g, 1, (int32_t)kind, flags, (hipStream_t)stream, default_config(), out,
+                           weighted ? lsh->weights : nullptr, &spec);
+}
+
 scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_kind kind,
                                    uint32_t flags, void *stream, scan_index **outs) {
   return build_index_batch(gs, count, (int32_t)kind, flags, (hipStream_t)stream, default_config(),
@@ -474,7 +491,8 @@ scan_status scan_segmented_sort(const int64_t *seg_off, int64_t nseg, const doub
   const int64_t total = seg_off[nseg];
   if (total > 0 && (!keys || !ids || !keys_out || !ids_out)) return fail(SCAN_EINVAL, "null argument");
   for (int64_t i = 0; i < total; ++i) {
-    if (!(keys[i] > 0.0) || std::isinf(keys[i])) return fail(SCAN_EINVAL, "keys must be positive and finite");
+    if (!std::isfinite(keys[i]) || (keys[i] == 0.0 && std::signbit(keys[i])))
+      return fail(SCAN_EINVAL, "keys must be finite and not -0");
     if (ids[i] < 0 || ids[i] == INT32_MAX) return fail(SCAN_EINVAL, "ids must be in [0, INT32_MAX)");
   }
   return segmented_sort_values(seg_off, nseg, keys, ids, keys_out, ids_out);

@@ -487,7 +487,7 @@ class HostPack {
 
 scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint32_t flags,
                               hipStream_t s, const IntersectConfig &cfg, scan_index **outs,
-                              const double *weights) {
+                              const double *weights, const LshSpec *lsh) {
   if (G < 0 || (G > 0 && (!gs || !outs))) return fail(SCAN_EINVAL, "bad batch arguments");
   for (int32_t g = 0; g < G; ++g) {
     outs[g] = nullptr;
@@ -500,6 +500,15 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     return fail(SCAN_EINVAL, "the weighted cosine takes one graph and its edge weights (scan_build_index_weighted)");
   if (!weighted && weights) return fail(SCAN_EINVAL, "edge weights given for an unweighted similarity");
   if (weighted && (flags & SCAN_KEEP_COUNTS)) return fail(SCAN_EINVAL, "the weighted cosine has no intersection counts");
+  if (lsh) {
+    if (G != 1) return fail(SCAN_EINVAL, "approximate builds take one graph");
+    if (lsh->samples < 64 || lsh->samples > 4096 || lsh->samples % 64)
+      return fail(SCAN_EINVAL, "LSH samples must be a multiple of 64 in [64, 4096]");
+    const bool need_gauss = kind != SCAN_SIM_JACCARD;
+    if ((need_gauss && !lsh->gauss) || (!need_gauss && !lsh->perm))
+      return fail(SCAN_EINVAL, "SimHash needs the Gaussian draws, MinHash the permutation");
+    if (flags & SCAN_KEEP_COUNTS) return fail(SCAN_EINVAL, "approximate similarities have no intersection counts");
+  }
   if (flags & ~(uint32_t)(SCAN_VALIDATE | SCAN_KEEP_SIMS | SCAN_KEEP_COUNTS | SCAN_PROFILE)) return fail(SCAN_EINVAL, "unknown build flags 0x%x", flags);
   if (cfg.small_max < 1 || cfg.small_max > 4096 || cfg.spc < 1 || cfg.spc > 1024 || cfg.wbits < 10 || cfg.wbits > 24)
     return fail(SCAN_EINVAL, "bad intersection config");
@@ -629,6 +638,25 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     }
     if (flags & SCAN_VALIDATE) SCAN_TRY(check_weights(w_dev, NNZ, tmp, s));
   }
+  LshSpec lsh_dev;  // the draws on the device
+  if (lsh && NNZ > 0) {
+    lsh_dev.samples = lsh->samples;
+    lsh_dev.gauss = lsh->gauss;
+    lsh_dev.perm = lsh->perm;
+    if (!gs[0].on_device) {
+      if (kind == SCAN_SIM_JACCARD) {
+        uint32_t *dp;
+        SCAN_TRY(tmp.alloc(&dp, N));
+        SCAN_HIP_TRY(hipMemcpyAsync(dp, lsh->perm, (size_t)N * 4, hipMemcpyHostToDevice, s));
+        lsh_dev.perm = dp;
+      } else {
+        double *dg;
+        SCAN_TRY(tmp.alloc(&dg, N * (int64_t)lsh->samples));
+        SCAN_HIP_TRY(hipMemcpyAsync(dg, lsh->gauss, (size_t)N * lsh->samples * 8, hipMemcpyHostToDevice, s));
+        lsh_dev.gauss = dg;
+      }
+    }
+  }
   // Index arrays (their sizes do not depend on the degrees): allocated while
   // the device runs the kernels above.
   int32_t *no_ids, *co_ids, *counts = nullptr;
@@ -691,11 +719,17 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       ist.ev_end = prof->ev[3];
       ist.host_counts = prof->plan_counts;
     }
+    hipEvent_t ev_end = ist.ev_end;
+    if (lsh) ist.ev_end = nullptr;  // recorded after the approximate pass
     if (weighted)
       SCAN_TRY(weighted_similarity_all(N, NNZ, off_u, deg, adj_u, w_dev, sims, tmp, s, ist.ev_start, ist.ev_mid,
                                        ist.ev_end));
     else
       SCAN_TRY(intersect_all(cfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
+    if (lsh) {
+      SCAN_TRY(lsh_overwrite(lsh_dev, N, NNZ, off_u, adj_u, weighted ? w_dev : nullptr, kind, sims, tmp, s));
+      if (ev_end) SCAN_HIP_TRY(hipEventRecord(ev_end, s));
+    }
     if (prof) {
       prof->window_bits = ist.wbits;
       prof->intersect_launches = ist.launches;

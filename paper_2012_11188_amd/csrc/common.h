@@ -24,15 +24,19 @@ __device__ __forceinline__ double similarity(int kind, int64_t c, int64_t a_u, i
   return (double)c / (double)(a_u + a_v - c);
 }
 
-// Order key for "similarity descending": similarities lie in (0, 1], so the
-// IEEE bit pattern of a positive double orders like its value and the
-// complement orders the other way. Sorting (key, id) ascending gives
-// similarity descending, ties by id ascending.
+// Order key for "similarity descending". The IEEE bits of a double, with the
+// sign bit flipped for non-negative values and every bit flipped for negative
+// ones, order like the values (the usual radix-sort transform); the complement
+// orders the other way. Exact similarities lie in (0, 1]; SimHash estimates
+// cos(pi h / k) are negative for h > k / 2, so negatives must order too.
+// Sorting (key, id) ascending gives similarity descending, ties by id
+// ascending.
 __device__ __forceinline__ uint64_t desc_key(double s) {
-  return ~(uint64_t)__double_as_longlong(s);
+  const uint64_t b = (uint64_t)__double_as_longlong(s);
+  return (b >> 63) ? b : ~(b ^ 0x8000000000000000ull);
 }
 __device__ __forceinline__ double key_to_sim(uint64_t k) {
-  return __longlong_as_double((long long)~k);
+  return __longlong_as_double((long long)((k >> 63) ? k : ~k ^ 0x8000000000000000ull));
 }
 __device__ __forceinline__ bool key_less(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
   return ka < kb || (ka == kb && ia < ib);

@@ -35,11 +35,24 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
                           const int32_t *deg, const int32_t *adj, int kind, double *sims,
                           int32_t *counts, int device, hipStream_t s, IntersectStats *stats);
 
+// Approximate similarities (lsh.hip): k samples, and the random draws on
+// the device (gauss n x k for SimHash, perm for MinHash).
+struct LshSpec {
+  int32_t samples = 0;
+  const double *gauss = nullptr;
+  const uint32_t *perm = nullptr;
+};
+
 // Weighted cosine of every edge into both CSR slots of sims (weighted.hip);
 // events (may be null) before the square sums, before the products, after.
 scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, const int32_t *deg,
                                     const int32_t *adj, const double *w, double *sims, DevArena &tmp,
                                     hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end);
+// Overwrites sims of the edges between two high-degree vertices with their
+// SimHash (cosine kinds) or k-partition MinHash (Jaccard) estimates; w may
+// be null (unweighted). spec's pointers are device pointers.
+scan_status lsh_overwrite(const LshSpec &spec, int64_t n, int64_t nnz, const int64_t *off, const int32_t *adj,
+                          const double *w, int kind, double *sims, DevArena &tmp, hipStream_t s);
 // SCAN_EGRAPH unless every weight is finite (waits for the stream).
 scan_status check_weights(const double *w, int64_t nnz, DevArena &tmp, hipStream_t s);
 
@@ -130,10 +143,12 @@ void index_release(scan_index *ix);
 scan_status build_index(const scan_csr *g, int32_t kind, uint32_t flags, hipStream_t stream,
                         const IntersectConfig &cfg, scan_index **out);
 // weights: per-slot edge weights (kind SCAN_SIM_WEIGHTED_COSINE, one graph
-// only), on the same side (host or device) as the graph.
+// only), on the same side (host or device) as the graph. lsh (one graph only):
+// approximate the edges between high-degree vertices; its draws are on the
+// graph's side too.
 scan_status build_index_batch(const scan_csr *gs, int32_t count, int32_t kind, uint32_t flags,
                               hipStream_t stream, const IntersectConfig &cfg, scan_index **outs,
-                              const double *weights = nullptr);
+                              const double *weights = nullptr, const LshSpec *lsh = nullptr);
 
 // Runs `count` queries. mu/eps host arrays; memberships[i] / is_core[i] are
 // device pointers (is_core may hold nulls). Slots are workspaces, one per

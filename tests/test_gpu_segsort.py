@@ -81,6 +81,20 @@ def test_segsort_errors():
     with pytest.raises(scan.ScanError):
         scan.scan_segmented_sort(np.array([0, 2, 1]), np.ones(2), np.arange(2))
     with pytest.raises(scan.ScanError):
-        scan.scan_segmented_sort(np.array([0, 2]), np.array([1.0, -1.0]), np.arange(2))
+        scan.scan_segmented_sort(np.array([0, 2]), np.array([1.0, np.nan]), np.arange(2))
+    with pytest.raises(scan.ScanError):
+        scan.scan_segmented_sort(np.array([0, 2]), np.array([1.0, -0.0]), np.arange(2))
     with pytest.raises(scan.ScanError):
         scan.scan_segmented_sort(np.array([0, 1]), np.array([1.0]), np.array([2**31 - 1]))
+
+
+def test_segsort_negative_keys():
+    # approximate similarities (cos(pi h / k)) can be negative: signed keys
+    # in every segment class, with ties
+    lengths = [1, 7, 33, 64, 65, 300, 1024, 1025, 4097, 9000]
+    seg_off, keys, ids = make(lengths, 9, 40)
+    keys = keys - 0.6  # about 60% negative
+    assert (keys < 0).any() and (keys > 0).any()
+    ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
+    eko, eio = expected(seg_off, keys, ids)
+    assert np.array_equal(ko, eko) and np.array_equal(io, eio)
