@@ -720,12 +720,16 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       ist.host_counts = prof->plan_counts;
     }
     hipEvent_t ev_end = ist.ev_end;
-    if (lsh) ist.ev_end = nullptr;  // recorded after the approximate pass
+    IntersectConfig icfg = cfg;
+    if (lsh) {  // the edges between two high-degree vertices are left to the approximate pass
+      ist.ev_end = nullptr;  // recorded after it
+      icfg.skip_deg = kind == SCAN_SIM_JACCARD ? 3 * lsh->samples / 2 : lsh->samples;
+    }
     if (weighted)
       SCAN_TRY(weighted_similarity_all(N, NNZ, off_u, deg, adj_u, w_dev, sims, tmp, s, ist.ev_start, ist.ev_mid,
-                                       ist.ev_end));
+                                       ist.ev_end, icfg.skip_deg));
     else
-      SCAN_TRY(intersect_all(cfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
+      SCAN_TRY(intersect_all(icfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
     if (lsh) {
       SCAN_TRY(lsh_overwrite(lsh_dev, N, NNZ, off_u, adj_u, weighted ? w_dev : nullptr, kind, sims, tmp, s));
       if (ev_end) SCAN_HIP_TRY(hipEventRecord(ev_end, s));

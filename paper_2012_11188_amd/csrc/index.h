@@ -16,6 +16,8 @@ struct IntersectConfig {
   int32_t spc = 512;        // row slots per chunk of a larger owner
   int32_t wbits = 20;       // LDS bitmap window of 2^wbits ids (clamped to LDS)
   bool search_windows = false;  // several windows: search row ranges instead of tabling them
+  int32_t skip_deg = 0x7fffffff;  // edges whose endpoints both exceed this degree are left unwritten
+                                  // (approximate builds overwrite them)
 };
 
 struct IntersectStats {
@@ -47,7 +49,8 @@ struct LshSpec {
 // events (may be null) before the square sums, before the products, after.
 scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, const int32_t *deg,
                                     const int32_t *adj, const double *w, double *sims, DevArena &tmp,
-                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end);
+                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end,
+                                    int32_t skip_deg = 0x7fffffff);
 // Overwrites sims of the edges between two high-degree vertices with their
 // SimHash (cosine kinds) or k-partition MinHash (Jaccard) estimates; w may
 // be null (unweighted). spec's pointers are device pointers.

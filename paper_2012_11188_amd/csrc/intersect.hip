@@ -202,7 +202,7 @@ static inline size_t small_lds_bytes(int small_max) {
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
     const int32_t *list, const int32_t *countp, int32_t *claim, int small_max, const int64_t *off,
-    const int32_t *deg, const int32_t *adj, int kind, double *sims, int32_t *counts) {
+    const int32_t *deg, const int32_t *adj, int kind, double *sims, int32_t *counts, int32_t skip) {
   const int32_t count = *countp;
   __shared__ int32_t s_idx;
   extern __shared__ unsigned char smem[];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
         d = deg[u];
         row[i] = u;
       }
-      const bool low = i < dh && is_lower(u, d, h, dh);
+      const bool low = i < dh && is_lower(u, d, h, dh) && d <= skip;
       const uint64_t m = __ballot(low);
       int32_t base = 0;
       if (m) {
@@ -360,7 +360,7 @@ template <bool kOneWindow>
 __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     const BigChunk *chunks, PlanCounts *pc, int spc, int wbits, int64_t n,
     const int64_t *off, const int32_t *deg, const int32_t *adj, const int32_t *wt, int32_t nwin, int kind,
-    double *sims, int32_t *counts) {
+    double *sims, int32_t *counts, int32_t skip) {
   extern __shared__ unsigned char smem[];
   const int64_t W = (int64_t)1 << wbits;
   const int nwords = (int)(W >> 5);
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       if (e < m) {
         u = adj[s0 + e];
         du = deg[u];
-        low = is_lower(u, du, h, dh);
+        low = is_lower(u, du, h, dh) && du <= skip;
       }
       const uint64_t mk = __ballot(low);
       int32_t base = 0;
@@ -704,11 +704,11 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
     }
     if (h.heavy)  // the longer rows first
       k_small_owner<kSmallWaves><<<h.heavy, kSmallWaves * kWave, lds, s>>>(
-          heavy_list, &pc->heavy, nullptr, cfg.small_max, off, deg, adj, kind, sims, counts);
+          heavy_list, &pc->heavy, nullptr, cfg.small_max, off, deg, adj, kind, sims, counts, cfg.skip_deg);
     if (h.small) {
       const int cap = std::min<int>(cfg.small_max, kLightDeg);  // light rows: LDS sized for them
       k_small_owner<1><<<h.small, kWave, small_lds_bytes(cap), s>>>(small_list, &pc->small, nullptr, cap, off,
-                                                                    deg, adj, kind, sims, counts);
+                                                                    deg, adj, kind, sims, counts, cfg.skip_deg);
     }
     SCAN_HIP_TRY(hipGetLastError());
   }
@@ -736,10 +736,10 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
     const int grid = (int)std::min<int64_t>((int64_t)cus * per_cu, h.big);
     if (one)
       k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nullptr,
-                                                       nwin, kind, sims, counts);
+                                                       nwin, kind, sims, counts, cfg.skip_deg);
     else
       k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, wt,
-                                                        nwin, kind, sims, counts);
+                                                        nwin, kind, sims, counts, cfg.skip_deg);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);

@@ -17,8 +17,9 @@
 //                the signs form one 64-bit word by ballot.
 //   k_minhash    one wavefront per high vertex: k bins in LDS, atomicMin of
 //                perm[x] over N[v].
-//   k_estimate   one wavefront per high vertex: its lanes take the row's
-//                slots and overwrite those whose other end is high too.
+//   k_estimate   one wavefront per piece of 64 slots of a high vertex's row
+//                (pieces numbered by a prefix over the vertices): the slots
+//                whose other end is high too are overwritten.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -33,6 +34,13 @@ namespace {
 constexpr int kLshThreads = 256;
 constexpr int kLshWaves = kLshThreads / kWave;
 constexpr int kLshBatch = 16;  // SimHash row entries whose coordinates are loaded together
+constexpr int kLshPiece = 64;  // row slots per estimate work item
+constexpr int kShBigDeg = 512;   // SimHash: vertices of higher degree go to the block kernel
+constexpr int kShChunk = 128;    // row entries staged in LDS per round of the block kernel
+constexpr int kShThreads = 256;
+constexpr int kShUnroll = 8;     // entries whose LDS values the summing wave reads ahead
+constexpr int kShWaves = kShThreads / kWave;
+constexpr int kMhGroup = 16;   // lanes comparing one pair of MinHash sketches
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -66,43 +74,142 @@ __global__ __launch_bounds__(kLshThreads) void k_simhash(const int64_t *off, con
     const int64_t v = t / groups;
     const int32_t g = (int32_t)(t - v * groups);
     const int64_t o = uniform64(off[v]), d = uniform64(off[v + 1]) - o;
-    if (!high(SCAN_SIM_COSINE, d, k)) continue;
+    if (!high(SCAN_SIM_COSINE, d, k) || d > kShBigDeg) continue;  // longer rows: k_simhash_big
     const double *col = gauss + g * kWave + lane;  // direction g * 64 + lane, row x at col[x * k]
     double acc = 0.0;
     bool self = false;
+    // The row goes 64 entries at a time (the next chunk's ids and weights
+    // loaded while this one is summed; loads past the row's end are clamped
+    // to its last entry). Inside a chunk the coordinates are gathered one
+    // batch of kLshBatch entries ahead of the in-order additions, in two
+    // register sets that swap roles (entries past the chunk's end are
+    // gathered but not added).
+    auto load = [&](int64_t c, int32_t &x, double &wx) {
+      const int64_t q = o + (c + lane < d ? c + lane : d - 1);
+      x = adj[q];
+      wx = w ? w[q] : 1.0;
+    };
+    int32_t xr;
+    double wr;
+    load(0, xr, wr);
     for (int64_t c = 0; c < d; c += kWave) {
-      const int64_t p = c + lane;
-      const int64_t q = o + (p < d ? p : d - 1);
-      const int32_t xr = adj[q];
-      const double wr = w ? w[q] : 1.0;
       const int m = (int)(d - c < kWave ? d - c : kWave);
-      // kLshBatch row entries at a time: their coordinates are loaded
-      // together (entries past m re-read entry m - 1 and are not added), then
-      // added in order.
-      for (int j0 = 0; j0 < m; j0 += kLshBatch) {
-        int32_t xs[kLshBatch];
-        double gs[kLshBatch];
+      int32_t xn;
+      double wn;
+      load(c + kWave < d ? c + kWave : c, xn, wn);
+      auto gather = [&](int j0, double *gs) {
 #pragma unroll
         for (int u = 0; u < kLshBatch; ++u) {
           const int j = j0 + u < m ? j0 + u : m - 1;
-          xs[u] = __builtin_amdgcn_readlane(xr, j);
-          gs[u] = col[(int64_t)xs[u] * k];
+          gs[u] = col[(int64_t)__builtin_amdgcn_readlane(xr, j) * k];
         }
+      };
+      auto add = [&](int j0, const double *gs) {
 #pragma unroll
         for (int u = 0; u < kLshBatch; ++u) {
           if (j0 + u < m) {
-            if (!self && xs[u] > v) {  // the self term (w(v, v) = 1) at its place
+            if (!self && __builtin_amdgcn_readlane(xr, j0 + u) > v) {  // the self term (w(v, v) = 1) at its place
               acc += 1.0 * col[v * (int64_t)k];
               self = true;
             }
             acc += lane_f64(wr, j0 + u) * gs[u];
           }
         }
+      };
+      double ga[kLshBatch], gb[kLshBatch];
+      gather(0, ga);
+      for (int j0 = 0; j0 < m; j0 += 2 * kLshBatch) {
+        gather(j0 + kLshBatch, gb);
+        add(j0, ga);
+        if (j0 + kLshBatch >= m) break;
+        gather(j0 + 2 * kLshBatch, ga);
+        add(j0 + kLshBatch, gb);
       }
+      xr = xn;
+      wr = wn;
     }
     if (!self) acc += 1.0 * col[v * (int64_t)k];
     const uint64_t bits = __ballot(acc >= 0.0);
     if (lane == 0) words[v * groups + g] = bits;
+  }
+}
+
+// big[] = the high vertices of degree > kShBigDeg, *nbig their number.
+__global__ void k_simhash_list(const int64_t *off, int64_t n, int32_t k, int32_t *big, int32_t *nbig) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = off[v + 1] - off[v];
+    if (high(SCAN_SIM_COSINE, d, k) && d > kShBigDeg) big[atomicAdd(nbig, 1)] = (int32_t)v;
+  }
+}
+
+// SimHash words of the long rows: one workgroup per (vertex, group of 64
+// directions). Per round, all waves gather the coordinates of kShChunk row
+// entries into LDS (a wave's gathers are issued back to back, so hundreds
+// are in flight at once), then wave 0 adds them in ascending order, lane i
+// for direction g * 64 + i, with the self term at its place.
+__global__ __launch_bounds__(kShThreads) void k_simhash_big(const int64_t *off, const int32_t *adj, const double *w,
+                                                            const double *gauss, int32_t k, const int32_t *big,
+                                                            const int32_t *nbig, uint64_t *words) {
+  extern __shared__ double st[];           // [kShChunk][64] coordinates
+  __shared__ int32_t sid[kShChunk];        // the entries' ids
+  __shared__ double sw[kShChunk];          // and weights
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  const int32_t groups = k / kWave;
+  const int64_t items = (int64_t)uniform(*nbig) * groups;
+  for (int64_t t = blockIdx.x; t < items; t += gridDim.x) {
+    const int64_t v = big[t / groups];
+    const int32_t g = (int32_t)(t % groups);
+    const int64_t o = uniform64(off[v]), d = uniform64(off[v + 1]) - o;
+    const double *col = gauss + g * kWave + lane;
+    double acc = 0.0;
+    bool self = false;
+    for (int64_t c = 0; c < d; c += kShChunk) {
+      const int m = (int)(d - c < kShChunk ? d - c : kShChunk);
+      __syncthreads();  // the previous round's readers are done
+      // entries wave, wave + kShWaves, ...: ids first (one vector load), then
+      // every gather of the wave, then the LDS stores
+      constexpr int kPer = kShChunk / kShWaves;
+      const int jl = wave + kShWaves * lane;  // the entry whose id this lane loads
+      const int32_t xl = jl < m ? adj[o + c + jl] : 0;
+      if (lane < kPer && jl < m) {
+        sid[jl] = xl;
+        sw[jl] = w ? w[o + c + jl] : 1.0;
+      }
+      double gv[kPer];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) gv[q] = col[(int64_t)__builtin_amdgcn_readlane(xl, q) * k];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q)
+        if (wave + kShWaves * q < m) st[(wave + kShWaves * q) * kWave + lane] = gv[q];
+      __syncthreads();
+      if (wave == 0) {
+        for (int j0 = 0; j0 < m; j0 += kShUnroll) {
+          int32_t xs[kShUnroll];
+          double ws[kShUnroll], gs[kShUnroll];
+#pragma unroll
+          for (int u = 0; u < kShUnroll; ++u) {  // entries past m read stale LDS and are not added
+            xs[u] = sid[j0 + u];
+            ws[u] = sw[j0 + u];
+            gs[u] = st[(j0 + u) * kWave + lane];
+          }
+#pragma unroll
+          for (int u = 0; u < kShUnroll; ++u) {
+            if (j0 + u < m) {
+              if (!self && xs[u] > v) {
+                acc += 1.0 * col[v * (int64_t)k];
+                self = true;
+              }
+              acc += ws[u] * gs[u];
+            }
+          }
+        }
+      }
+    }
+    if (wave == 0) {
+      if (!self) acc += 1.0 * col[v * (int64_t)k];
+      const uint64_t bits = __ballot(acc >= 0.0);
+      if (lane == 0) words[v * groups + g] = bits;
+    }
   }
 }
 
@@ -129,22 +236,61 @@ __global__ __launch_bounds__(kLshThreads) void k_minhash(const int64_t *off, con
   }
 }
 
+// cnt[u] = pieces of kLshPiece slots of u's row when u is high, else 0.
+__global__ void k_lsh_pieces(const int64_t *off, int64_t n, int kind, int32_t k, int32_t *cnt) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = off[u + 1] - off[u];
+    cnt[u] = high(kind, d, k) ? (int32_t)((d + kLshPiece - 1) / kLshPiece) : 0;
+  }
+}
+
+// One wavefront per piece (P = exclusive prefix of the pieces, P[n] their
+// number): the piece's slots whose other end is high too get the estimate.
+// SimHash: a lane per slot. MinHash: four groups of 16 lanes, a group per
+// slot; lane l of a group compares bins 4 (l + 16 i) .. 4 (l + 16 i) + 3, so
+// each load instruction of a group reads 256 contiguous bytes of a sketch.
 __global__ __launch_bounds__(kLshThreads) void k_estimate(const int64_t *off, const int32_t *adj, int64_t n,
-                                                          int kind, int32_t k, const uint64_t *words,
-                                                          const uint32_t *sk, const double *table, double *sims) {
+                                                          int kind, int32_t k, const int64_t *P,
+                                                          const uint64_t *words, const uint32_t *sk,
+                                                          const double *table, double *sims) {
   const int lane = lane_id();
   const int64_t waves = (int64_t)gridDim.x * kLshWaves;
-  for (int64_t u = uniform64(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave); u < n; u += waves) {
-    const int64_t o = uniform64(off[u]), d = uniform64(off[u + 1]) - o;
-    if (!high(kind, d, k)) continue;
-    for (int64_t p = lane; p < d; p += kWave) {
-      const int64_t v = adj[o + p];
-      if (!high(kind, off[v + 1] - off[v], k)) continue;
-      double x;
-      if (kind == SCAN_SIM_JACCARD) {
+  const int64_t T = uniform64(P[n]);
+  for (int64_t t = uniform64(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave); t < T; t += waves) {
+    int64_t lo = 0, hi = n;  // the u with P[u] <= t < P[u + 1]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (uniform64(P[mid]) <= t) lo = mid;
+      else hi = mid;
+    }
+    const int64_t u = lo, o = uniform64(off[u]), d = uniform64(off[u + 1]) - o;
+    const int64_t p0 = (t - uniform64(P[u])) * kLshPiece;
+    if (kind != SCAN_SIM_JACCARD) {
+      const int64_t p = p0 + lane;
+      if (p < d && p < p0 + kLshPiece) {
+        const int64_t v = adj[o + p];
+        if (high(kind, off[v + 1] - off[v], k)) {
+          const int32_t groups = k / kWave;
+          int32_t h = 0;
+          for (int32_t i = 0; i < groups; ++i) h += __popcll(words[u * groups + i] ^ words[v * groups + i]);
+          sims[o + p] = table[h];
+        }
+      }
+      continue;
+    }
+    const int grp = lane / kMhGroup, gl = lane % kMhGroup;
+    for (int r = 0; r < kLshPiece / (kWave / kMhGroup); ++r) {
+      const int64_t p = p0 + r * (kWave / kMhGroup) + grp;
+      bool on = p < d;
+      int64_t v = 0;
+      if (on) {
+        v = adj[o + p];
+        on = high(kind, off[v + 1] - off[v], k);
+      }
+      int32_t match = 0, empty = 0;
+      if (on) {
         const uint4 *a = (const uint4 *)(sk + u * k), *b = (const uint4 *)(sk + v * k);
-        int32_t match = 0, empty = 0;
-        for (int32_t i = 0; i < k / 4; ++i) {
+        for (int32_t i = gl; i < k / 4; i += kMhGroup) {
           const uint4 ea = a[i], eb = b[i];
           const uint32_t av[4] = {ea.x, ea.y, ea.z, ea.w}, bv[4] = {eb.x, eb.y, eb.z, eb.w};
 #pragma unroll
@@ -153,14 +299,12 @@ __global__ __launch_bounds__(kLshThreads) void k_estimate(const int64_t *off, co
             else if (av[j] == bv[j]) ++match;
           }
         }
-        x = (double)match / (double)(k - empty);
-      } else {
-        const int32_t groups = k / kWave;
-        int32_t h = 0;
-        for (int32_t i = 0; i < groups; ++i) h += __popcll(words[u * groups + i] ^ words[v * groups + i]);
-        x = table[h];
       }
-      sims[o + p] = x;
+      for (int m = kMhGroup / 2; m > 0; m >>= 1) {  // sums over the group (all lanes take part)
+        match += __shfl_xor(match, m, kWave);
+        empty += __shfl_xor(empty, m, kWave);
+      }
+      if (on && gl == 0) sims[o + p] = (double)match / (double)(k - empty);
     }
   }
 }
@@ -200,10 +344,26 @@ scan_status lsh_overwrite(const LshSpec &spec, int64_t n, int64_t nnz, const int
     SCAN_TRY(tmp.alloc(&table, k + 1));
     SCAN_HIP_TRY(hipMemcpyAsync(table, t.data(), t.size() * 8, hipMemcpyHostToDevice, s));
     SCAN_TRY(tmp.alloc(&words, n * (int64_t)(k / kWave)));
+    int32_t *big, *nbig;
+    SCAN_TRY(tmp.alloc(&big, n));
+    SCAN_TRY(tmp.alloc(&nbig, 1));
+    SCAN_HIP_TRY(hipMemsetAsync(nbig, 0, 4, s));
+    k_simhash_list<<<grid_for(n, 256), 256, 0, s>>>(off, n, k, big, nbig);
+    const size_t lds = (size_t)kShChunk * kWave * 8;
+    SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_simhash_big, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    k_simhash_big<<<1024, kShThreads, lds, s>>>(off, adj, w, spec.gauss, k, big, nbig, words);
     k_simhash<<<grid_for(n * (k / kWave) * kWave, kLshThreads), kLshThreads, 0, s>>>(off, adj, w, spec.gauss, n, k,
                                                                                     words);
   }
-  k_estimate<<<grid_for(n * kWave, kLshThreads), kLshThreads, 0, s>>>(off, adj, n, kind, k, words, sk, table, sims);
+  int32_t *cnt;
+  int64_t *P, *ws;
+  SCAN_TRY(tmp.alloc(&cnt, n));
+  SCAN_TRY(tmp.alloc(&P, n + 1));
+  SCAN_TRY(tmp.alloc(&ws, scan_workspace_elems(n)));
+  k_lsh_pieces<<<grid_for(n, 256), 256, 0, s>>>(off, n, kind, k, cnt);
+  SCAN_TRY(exclusive_scan(cnt, P, n, ws, s));
+  k_estimate<<<grid_for(n * kWave / 16, kLshThreads), kLshThreads, 0, s>>>(off, adj, n, kind, k, P, words, sk, table,
+                                                                          sims);
   SCAN_HIP_TRY(hipGetLastError());
   if (kind != SCAN_SIM_JACCARD) SCAN_HIP_TRY(hipStreamSynchronize(s));  // the host table stays alive until here
   return SCAN_OK;

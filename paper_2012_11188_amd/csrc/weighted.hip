@@ -36,6 +36,10 @@ constexpr int kWThreads = 256;
 constexpr int kWWaves = kWThreads / kWave;
 constexpr int kWTile = 1024;                 // owner ids (and weights) per LDS tile
 constexpr int kWRows = 64;                   // row offsets staged at a time
+#ifndef SCAN_W_CHUNKS
+#define SCAN_W_CHUNKS 4
+#endif
+constexpr int kWChunks = SCAN_W_CHUNKS;      // 64-id chunks of a lower row loaded at once
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -123,7 +127,7 @@ struct WShared {
 
 __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const int32_t *deg, const int32_t *adj,
                                                        const double *w, const double *S, const int32_t *row_of,
-                                                       int64_t n, int64_t nnz, double *sims) {
+                                                       int64_t n, int64_t nnz, double *sims, int32_t skip) {
   __shared__ WShared sh;
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int64_t s0 = (int64_t)blockIdx.x * kWUnit, s1 = s0 + kWUnit < nnz ? s0 + kWUnit : nnz;
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
           u = adj[slot];
           du = deg[u];
         }
-        const bool low = in && (du < dh || (du == dh && u < h));
+        const bool low = in && (du < dh || (du == dh && u < h)) && du <= skip;
         const uint64_t m = __ballot(low);
         int32_t j0 = 0;
         if (m) {
@@ -192,17 +196,14 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
           bool ldone = uniform(sh.ldone[j]) != 0;
           const double whl = sh.whl[j];
           double acc = sh.acc[j];
-          while (c < du) {
-            const int32_t p = c + lane;
-            const bool in = p < du;
-            const int64_t q = ou + (in ? p : du - 1);  // clamped: both loads issue together
-            const int32_t xq = adj[q];
-            const double wq = w[q];
+          // One chunk of 64 positions from c: returns how many were in
+          // range (a prefix) and sets nx when the range ended inside it.
+          auto chunk = [&](int32_t xq, double wq) {
+            const bool in = c + lane < du;
             const int32_t x = in ? xq : INT_MAX;
             const double wl = in ? wq : 0.0;
             const bool valid = in && (last || x <= hi);
-            // lower_bound of x in the tile
-            int32_t lo = 0, len = tn;
+            int32_t lo = 0, len = tn;  // lower_bound of x in the tile
             while (len > 0) {
               const int32_t half = len >> 1;
               if (sh.tid[lo + half] < x) {
@@ -227,10 +228,29 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
               }
               acc += lane_f64(prod, k);
             }
-            c += cnt;
-            if (cnt < kWave) {
-              if (c < du) nx = __builtin_amdgcn_readlane(x, cnt);
-              break;
+            if (cnt < kWave && c + cnt < du) nx = __builtin_amdgcn_readlane(x, cnt);
+            return cnt;
+          };
+          // kWChunks chunks' loads are issued together (clamped into the
+          // row, so unconditionally), then the chunks are taken in order.
+          bool more = c < du;
+          while (more) {
+            int32_t xq[kWChunks];
+            double wq[kWChunks];
+#pragma unroll
+            for (int u = 0; u < kWChunks; ++u) {
+              const int32_t p = c + u * kWave + lane;
+              const int64_t q = ou + (p < du ? p : du - 1);
+              xq[u] = adj[q];
+              wq[u] = w[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kWChunks; ++u) {
+              if (more) {
+                const int cnt = chunk(xq[u], wq[u]);
+                c += cnt;
+                more = cnt == kWave && c < du;
+              }
             }
           }
           if (lane == 0) {
@@ -281,7 +301,8 @@ scan_status check_weights(const double *w, int64_t nnz, DevArena &tmp, hipStream
 
 scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, const int32_t *deg,
                                     const int32_t *adj, const double *w, double *sims, DevArena &tmp,
-                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end) {
+                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end,
+                                    int32_t skip_deg) {
   if (ev_start) SCAN_HIP_TRY(hipEventRecord(ev_start, s));
   if (nnz > 0) {
     const int64_t units = (nnz + kWUnit - 1) / kWUnit;
@@ -294,7 +315,7 @@ scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, 
     k_w_unit_rows<<<grid_for(n, 256), 256, 0, s>>>(off, n, row_of);
     SCAN_HIP_TRY(hipGetLastError());
     if (ev_mid) SCAN_HIP_TRY(hipEventRecord(ev_mid, s));
-    k_w_owner<<<(unsigned)units, kWThreads, 0, s>>>(off, deg, adj, w, S, row_of, n, nnz, sims);
+    k_w_owner<<<(unsigned)units, kWThreads, 0, s>>>(off, deg, adj, w, S, row_of, n, nnz, sims, skip_deg);
     SCAN_HIP_TRY(hipGetLastError());
   } else if (ev_mid) {
     SCAN_HIP_TRY(hipEventRecord(ev_mid, s));
