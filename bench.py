@@ -355,9 +355,19 @@ def lsh_timing(scan, torch, graphgen, g, off, adj, exact_ms, steps, k=256):
         ms, dev_ms, profs, _ = timed_builds(
             scan, torch, lambda: [scan.scan_build_index_lsh(off, adj, kind, k, gauss, perm, None, scan.SCAN_PROFILE)],
             steps, 1)
+        phases = {k_: med(profs, k_) for k_ in PHASES}
+        slots = int((hi[rows] & hi[g.adj]).sum())
+        entries = int((deg[hi] + 1).sum())  # sketched closed-neighbourhood entries
+        # sketches: SimHash gathers k coordinates (8 B) per entry, MinHash one
+        # permuted id (4 B) and the entry's id (4 B); estimates read two sketches
+        # per approximated slot (k bits, or k 4-byte bins) and write 8 B
+        sk_bytes = entries * (8 * k if kind == scan.COSINE else 8)
+        est_bytes = slots * ((2 * k // 8 if kind == scan.COSINE else 8 * k) + 8)
         out[name] = {"value": g.num_edges / (ms * 1e-3), "unit": "edges/s", "ms_per_step": ms,
-                     "device_ms_per_step": dev_ms, "phases_ms": {k_: med(profs, k_) for k_ in PHASES},
-                     "approximated_slots": int((hi[rows] & hi[g.adj]).sum()), "sketched_vertices": int(hi.sum()),
+                     "device_ms_per_step": dev_ms, "phases_ms": phases,
+                     "approximated_slots": slots, "sketched_vertices": int(hi.sum()),
+                     "sketch_bytes": sk_bytes, "estimate_bytes": est_bytes,
+                     "similarity_phase_gbs": (sk_bytes + est_bytes) / (phases["intersect_ms"] * 1e-3) / 1e9,
                      "over_exact_ms": ms - exact_ms}
         del gauss, perm
     return out
