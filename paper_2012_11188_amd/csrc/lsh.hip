@@ -12,9 +12,13 @@
 //   v's sketch is the least perm[x] over x in N[v] in bin b (0xffffffff when
 //   none). Estimate: matching non-empty bins / (k - bins empty in both).
 //
-//   k_simhash    one wavefront per (high vertex, group of 64 directions):
-//                lane i sums direction g * 64 + i over N[v] in ascending x;
+//   k_simhash_big  rows longer than kShBigDeg: one workgroup per (vertex,
+//                group of 64 directions); its wavefronts gather the
+//                coordinates of kShChunk row entries into LDS, then one of
+//                them adds them in ascending x (lane i: direction g * 64 + i);
 //                the signs form one 64-bit word by ballot.
+//   k_simhash    the other high rows: one wavefront per (vertex, group),
+//                gathering one batch of entries ahead of the additions.
 //   k_minhash    one wavefront per high vertex: k bins in LDS, atomicMin of
 //                perm[x] over N[v].
 //   k_estimate   one wavefront per piece of 64 slots of a high vertex's row
