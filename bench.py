@@ -36,7 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 METRIC = "index-build edges/s (R-MAT-20); query p50/p99 ms, batched vs one-at-a-time"
-COUNTERS = os.path.join(ROOT, "profiles", "k_big_owner_rmat20_counters.txt")
+def counters_file(workload: str) -> str:
+    """profiles/k_big_owner_<graph>_counters.txt for workload <graph>_..."""
+    return os.path.join(ROOT, "profiles", f"k_big_owner_{workload.split('_')[0]}_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_11188_amd", "csrc", "intersect.hip")
 
 
@@ -81,10 +83,11 @@ def counter_traffic(tune: dict, workload: str):
     """Measured HBM bytes per k_big_owner launch from the committed rocprofv3
     counter summary, if it was taken on this kernel source, workload and
     shape; else None and the reason."""
-    if not os.path.exists(COUNTERS):
+    path = counters_file(workload)
+    if not os.path.exists(path):
         return None, "no counter summary"
     kv = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
