@@ -658,16 +658,31 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     }
   }
   // Index arrays (their sizes do not depend on the degrees): allocated while
-  // the device runs the kernels above.
+  // the device runs the kernels above, as one block carved into 256-byte
+  // aligned arrays (each allocation may cross into the caller's allocator).
   int32_t *no_ids, *co_ids, *counts = nullptr;
-  double *no_sim, *co_thr, *sims;
-  SCAN_TRY(arena_alloc(*arena, &no_ids, NNZ));
-  SCAN_TRY(arena_alloc(*arena, &no_sim, NNZ));
-  SCAN_TRY(arena_alloc(*arena, &co_ids, NNZ));
-  SCAN_TRY(arena_alloc(*arena, &co_thr, NNZ));
-  if (flags & SCAN_KEEP_SIMS) SCAN_TRY(arena_alloc(*arena, &sims, NNZ));
-  else SCAN_TRY(tmp.alloc(&sims, NNZ));
-  if (flags & SCAN_KEEP_COUNTS) SCAN_TRY(arena_alloc(*arena, &counts, NNZ));
+  double *no_sim, *co_thr, *sims = nullptr;
+  {
+    size_t bytes = 0;
+    auto take = [&](size_t b) {
+      const size_t at = bytes;
+      bytes += (b + 255) & ~(size_t)255;
+      return at;
+    };
+    const size_t nz = (size_t)std::max<int64_t>(NNZ, 1);
+    const size_t o_no_ids = take(nz * 4), o_no_sim = take(nz * 8), o_co_ids = take(nz * 4), o_co_thr = take(nz * 8);
+    const size_t o_sims = (flags & SCAN_KEEP_SIMS) ? take(nz * 8) : 0;
+    const size_t o_counts = (flags & SCAN_KEEP_COUNTS) ? take(nz * 4) : 0;
+    unsigned char *block;
+    SCAN_TRY(arena_alloc(*arena, &block, (int64_t)bytes));
+    no_ids = (int32_t *)(block + o_no_ids);
+    no_sim = (double *)(block + o_no_sim);
+    co_ids = (int32_t *)(block + o_co_ids);
+    co_thr = (double *)(block + o_co_thr);
+    if (flags & SCAN_KEEP_SIMS) sims = (double *)(block + o_sims);
+    if (flags & SCAN_KEEP_COUNTS) counts = (int32_t *)(block + o_counts);
+  }
+  if (!sims) SCAN_TRY(tmp.alloc(&sims, NNZ));
 
   std::vector<unsigned> hdmax(G);
   SCAN_HIP_TRY(hipMemcpyAsync(hdmax.data(), d_dmax, (size_t)G * 4, hipMemcpyDeviceToHost, s));
