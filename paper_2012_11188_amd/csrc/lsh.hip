@@ -12,13 +12,11 @@
 //   v's sketch is the least perm[x] over x in N[v] in bin b (0xffffffff when
 //   none). Estimate: matching non-empty bins / (k - bins empty in both).
 //
-//   k_simhash_big  rows longer than kShBigDeg: one workgroup per (vertex,
-//                group of 64 directions); its wavefronts gather the
-//                coordinates of kShChunk row entries into LDS, then one of
-//                them adds them in ascending x (lane i: direction g * 64 + i);
-//                the signs form one 64-bit word by ballot.
-//   k_simhash    the other high rows: one wavefront per (vertex, group),
-//                gathering one batch of entries ahead of the additions.
+//   k_simhash_big  one workgroup per (high vertex, group of 64 directions):
+//                its wavefronts gather the coordinates of kShChunk row
+//                entries into LDS, then one of them adds them in ascending x
+//                (lane i: direction g * 64 + i); the signs form one 64-bit
+//                word by ballot.
 //   k_minhash    one wavefront per high vertex: k bins in LDS, atomicMin of
 //                perm[x] over N[v].
 //   k_estimate   one wavefront per piece of 64 slots of a high vertex's row
@@ -37,9 +35,7 @@ namespace {
 
 constexpr int kLshThreads = 256;
 constexpr int kLshWaves = kLshThreads / kWave;
-constexpr int kLshBatch = 16;  // SimHash row entries whose coordinates are loaded together
 constexpr int kLshPiece = 64;  // row slots per estimate work item
-constexpr int kShBigDeg = 512;   // SimHash: vertices of higher degree go to the block kernel
 constexpr int kShChunk = 128;    // row entries staged in LDS per round of the block kernel
 constexpr int kShThreads = 256;
 constexpr int kShUnroll = 8;     // entries whose LDS values the summing wave reads ahead
@@ -54,100 +50,20 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Lane j's double (j wave-uniform).
-__device__ __forceinline__ double lane_f64(double v, int j) {
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)b, j);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(b >> 32), j);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
 __device__ __forceinline__ bool high(int kind, int64_t deg, int64_t k) {
   return kind == SCAN_SIM_JACCARD ? 2 * deg > 3 * k : deg > k;
 }
 
-// words[v * (k / 64) + g]: bit i is direction g * 64 + i.
-__global__ __launch_bounds__(kLshThreads) void k_simhash(const int64_t *off, const int32_t *adj, const double *w,
-                                                         const double *gauss, int64_t n, int32_t k,
-                                                         uint64_t *words) {
-  const int lane = lane_id();
-  const int32_t groups = k / kWave;
-  const int64_t waves = (int64_t)gridDim.x * kLshWaves;
-  for (int64_t t = uniform64(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave); t < n * groups;
-       t += waves) {
-    const int64_t v = t / groups;
-    const int32_t g = (int32_t)(t - v * groups);
-    const int64_t o = uniform64(off[v]), d = uniform64(off[v + 1]) - o;
-    if (!high(SCAN_SIM_COSINE, d, k) || d > kShBigDeg) continue;  // longer rows: k_simhash_big
-    const double *col = gauss + g * kWave + lane;  // direction g * 64 + lane, row x at col[x * k]
-    double acc = 0.0;
-    bool self = false;
-    // The row goes 64 entries at a time (the next chunk's ids and weights
-    // loaded while this one is summed; loads past the row's end are clamped
-    // to its last entry). Inside a chunk the coordinates are gathered one
-    // batch of kLshBatch entries ahead of the in-order additions, in two
-    // register sets that swap roles (entries past the chunk's end are
-    // gathered but not added).
-    auto load = [&](int64_t c, int32_t &x, double &wx) {
-      const int64_t q = o + (c + lane < d ? c + lane : d - 1);
-      x = adj[q];
-      wx = w ? w[q] : 1.0;
-    };
-    int32_t xr;
-    double wr;
-    load(0, xr, wr);
-    for (int64_t c = 0; c < d; c += kWave) {
-      const int m = (int)(d - c < kWave ? d - c : kWave);
-      int32_t xn;
-      double wn;
-      load(c + kWave < d ? c + kWave : c, xn, wn);
-      auto gather = [&](int j0, double *gs) {
-#pragma unroll
-        for (int u = 0; u < kLshBatch; ++u) {
-          const int j = j0 + u < m ? j0 + u : m - 1;
-          gs[u] = col[(int64_t)__builtin_amdgcn_readlane(xr, j) * k];
-        }
-      };
-      auto add = [&](int j0, const double *gs) {
-#pragma unroll
-        for (int u = 0; u < kLshBatch; ++u) {
-          if (j0 + u < m) {
-            if (!self && __builtin_amdgcn_readlane(xr, j0 + u) > v) {  // the self term (w(v, v) = 1) at its place
-              acc += 1.0 * col[v * (int64_t)k];
-              self = true;
-            }
-            acc += lane_f64(wr, j0 + u) * gs[u];
-          }
-        }
-      };
-      double ga[kLshBatch], gb[kLshBatch];
-      gather(0, ga);
-      for (int j0 = 0; j0 < m; j0 += 2 * kLshBatch) {
-        gather(j0 + kLshBatch, gb);
-        add(j0, ga);
-        if (j0 + kLshBatch >= m) break;
-        gather(j0 + 2 * kLshBatch, ga);
-        add(j0 + kLshBatch, gb);
-      }
-      xr = xn;
-      wr = wn;
-    }
-    if (!self) acc += 1.0 * col[v * (int64_t)k];
-    const uint64_t bits = __ballot(acc >= 0.0);
-    if (lane == 0) words[v * groups + g] = bits;
-  }
-}
-
-// big[] = the high vertices of degree > kShBigDeg, *nbig their number.
+// big[] = the high vertices, *nbig their number.
 __global__ void k_simhash_list(const int64_t *off, int64_t n, int32_t k, int32_t *big, int32_t *nbig) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int64_t d = off[v + 1] - off[v];
-    if (high(SCAN_SIM_COSINE, d, k) && d > kShBigDeg) big[atomicAdd(nbig, 1)] = (int32_t)v;
+    if (high(SCAN_SIM_COSINE, d, k)) big[atomicAdd(nbig, 1)] = (int32_t)v;
   }
 }
 
-// SimHash words of the long rows: one workgroup per (vertex, group of 64
-// directions). Per round, all waves gather the coordinates of kShChunk row
+// SimHash words, words[v * (k / 64) + g] with bit i for direction g * 64 + i:
+// one workgroup per (high vertex, group of 64 directions). Per round, all waves gather the coordinates of kShChunk row
 // entries into LDS (a wave's gathers are issued back to back, so hundreds
 // are in flight at once), then wave 0 adds them in ascending order, lane i
 // for direction g * 64 + i, with the self term at its place.
@@ -356,8 +272,6 @@ scan_status lsh_overwrite(const LshSpec &spec, int64_t n, int64_t nnz, const int
     const size_t lds = (size_t)kShChunk * kWave * 8;
     SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_simhash_big, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     k_simhash_big<<<1024, kShThreads, lds, s>>>(off, adj, w, spec.gauss, k, big, nbig, words);
-    k_simhash<<<grid_for(n * (k / kWave) * kWave, kLshThreads), kLshThreads, 0, s>>>(off, adj, w, spec.gauss, n, k,
-                                                                                    words);
   }
   int32_t *cnt;
   int64_t *P, *ws;
