@@ -178,12 +178,23 @@ __device__ __forceinline__ void write_edge(int kind, int64_t s, int64_t mirror, 
 
 // ---------------------------------------------------------------------------
 // Small owners (degree <= small_max): one workgroup per vertex, of one
-// wavefront up to degree kLightDeg and of kSmallWaves wavefronts above. The vertex's lower neighbours are compacted into LDS; if there
-// are any, its row goes into an LDS hash table (open addressing, load <= 1/2)
-// and the wavefronts take the lower neighbours in turn, streaming each one's
-// row 64 ids at a time and probing the table.
+// wavefront up to degree kLightDeg and of kSmallWaves wavefronts above. The
+// vertex's lower neighbours are compacted into LDS; if there are any, its row
+// goes into an LDS hash table (open addressing, load <= 1/2) and the lower
+// neighbours' rows are streamed through it: with one wavefront, each group of
+// kLightGroup lanes takes one lower neighbour (several rows per step, since
+// these rows are short); with several, the wavefronts take them in turn, 64
+// ids at a time.
 
 constexpr int kSmallWaves = 4;
+#ifndef SCAN_LIGHT_GROUP
+#define SCAN_LIGHT_GROUP 16
+#endif
+constexpr int kLightGroup = SCAN_LIGHT_GROUP;  // lanes per lower neighbour in the one-wavefront kernel
+#ifndef SCAN_HEAVY_GROUP
+#define SCAN_HEAVY_GROUP 32
+#endif
+constexpr int kHeavyGroup = SCAN_HEAVY_GROUP;  // and in the kSmallWaves kernel
 constexpr int32_t kEmpty = -1;
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t x, int tbits) {
@@ -264,41 +275,44 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
       while (atomicCAS(&tab[sl], kEmpty, x) != kEmpty) sl = (sl + 1) & (uint32_t)(tsize - 1);
     }
     __syncthreads();
-    for (int32_t j = wave; j < nlow; j += WAVES) {
-      const int32_t du = uniform(ldu[j]);
-      const int64_t ou = uniform64(lou[j]);
-      const int32_t e = uniform(le[j]);
+    // Each group of G lanes takes one lower neighbour (NG per wavefront, the
+    // wavefronts take successive sets) and streams its row G ids per step; a
+    // missing row has length 0. Loads are clamped into the row.
+    constexpr int G = WAVES == 1 ? kLightGroup : kHeavyGroup, NG = kWave / G;
+    constexpr uint64_t gmask = G == 64 ? ~0ull : (1ull << G) - 1;
+    const int grp = lane / G, gl = lane % G;
+    for (int32_t j0 = wave * NG; j0 < nlow; j0 += WAVES * NG) {
+      const int32_t j = j0 + grp;
+      const bool has = j < nlow;
+      const int32_t du = has ? ldu[j] : 0;
+      const int64_t ou = has ? lou[j] : 0;
+      int32_t dmaxg = 0;  // the longest of the NG rows
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+        if (j0 + g < nlow) dmaxg = max(dmaxg, uniform(ldu[j0 + g]));
       int32_t t = 0;
       int64_t mpos = -1;
-      // Loads are clamped into the row (lanes past its end re-read its last
-      // id and are masked out), so they need no branch.
-      constexpr int UNROLL = 1;
-      for (int32_t k0 = 0; k0 < du; k0 += UNROLL * kWave) {
-        int32_t x[UNROLL];
-#pragma unroll
-        for (int k = 0; k < UNROLL; ++k) x[k] = adj[ou + min(k0 + k * kWave + lane, du - 1)];
-#pragma unroll
-        for (int k = 0; k < UNROLL; ++k) {
-          const int32_t i = k0 + k * kWave + lane;
-          const bool valid = i < du;
-          uint32_t sl = hash_slot(x[k], tbits);
-          bool hit = false;
-          for (int32_t probe = 0; probe < tsize; ++probe) {  // ends at x or at an empty slot
-            const int32_t v = tab[sl];
-            if (v == x[k]) {
-              hit = true;
-              break;
-            }
-            if (v == kEmpty) break;
-            sl = (sl + 1) & (uint32_t)(tsize - 1);
+      for (int32_t k0 = 0; k0 < dmaxg; k0 += G) {
+        const int32_t i = k0 + gl;
+        const bool valid = i < du;
+        const int32_t x = adj[ou + (valid ? i : (du > 0 ? du - 1 : 0))];
+        uint32_t sl = hash_slot(x, tbits);
+        bool hit = false;
+        for (int32_t probe = 0; probe < tsize; ++probe) {  // ends at x or at an empty slot
+          const int32_t v = tab[sl];
+          if (v == x) {
+            hit = true;
+            break;
           }
-          t += __popcll(__ballot(valid && hit));
-          const uint64_t me = __ballot(valid && x[k] == h);
-          if (me) mpos = ou + k0 + k * kWave + (__ffsll((unsigned long long)me) - 1);
+          if (v == kEmpty) break;
+          sl = (sl + 1) & (uint32_t)(tsize - 1);
         }
+        const uint64_t m = __ballot(valid && hit), me = __ballot(valid && x == h);
+        t += __popcll((m >> (grp * G)) & gmask);
+        const uint64_t mine = (me >> (grp * G)) & gmask;
+        if (mine) mpos = ou + k0 + (__ffsll((unsigned long long)mine) - 1);
       }
-      // wave-uniform result: every lane stores the same values
-      write_edge(kind, oh + e, mpos, t, du, dh, sims, counts);
+      if (has && gl == 0) write_edge(kind, oh + le[j], mpos, t, du, dh, sims, counts);
     }
   }
 }
