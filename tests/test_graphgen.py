@@ -97,3 +97,35 @@ def test_owner_split():
                     es += 1
                     ws += min(deg[u], deg[v])
         assert (sp["edges_small"], sp["w_small"]) == (es, ws)
+
+
+def test_edge_weights_symmetric_and_in_range():
+    g = graphgen.rmat(10, 8, seed=6)
+    w = graphgen.edge_weights(g, 9, 0.05, 1.0)
+    assert w.shape == (g.nnz,) and w.min() >= 0.05 and w.max() < 1.0
+    rows = np.repeat(np.arange(g.n), np.diff(g.off))
+    # the weight of (u, v) equals that of (v, u): compare via a dict of pairs
+    pair = {(int(u), int(v)): x for u, v, x in zip(rows, g.adj, w)}
+    assert all(pair[(v, u)] == x for (u, v), x in pair.items())
+    assert np.array_equal(w, graphgen.edge_weights(g, 9, 0.05, 1.0))  # seeded
+    assert not np.array_equal(w, graphgen.edge_weights(g, 10, 0.05, 1.0))
+    assert len(np.unique(w)) > 0.9 * g.num_edges  # full-mantissa draws, no repeats to speak of
+
+
+def test_gaussians_moments_and_determinism():
+    x = graphgen.gaussians(4000, 64, 3)
+    assert x.shape == (4000, 64)
+    assert abs(x.mean()) < 0.01 and abs(x.std() - 1.0) < 0.01
+    # standard normal tails: about 4.55% beyond 2 sigma
+    assert abs((np.abs(x) > 2).mean() - 0.0455) < 0.003
+    assert np.array_equal(x, graphgen.gaussians(4000, 64, 3))
+    assert np.array_equal(x[:10], graphgen.gaussians(10, 64, 3))  # coordinate c = x * k + i: prefixes agree
+
+
+def test_permutation_is_a_permutation():
+    for n in (1, 2, 17, 10000):
+        p = graphgen.permutation(n, 5)
+        assert p.dtype == np.uint32 and np.array_equal(np.sort(p), np.arange(n, dtype=np.uint32))
+    p = graphgen.permutation(10000, 5)
+    assert np.array_equal(p, graphgen.permutation(10000, 5))
+    assert (p == np.arange(10000)).mean() < 0.01  # not close to the identity
