@@ -174,3 +174,18 @@ def test_lsh_rmat20_sampled(kind):
     same = rows[1:] == rows[:-1]
     d = np.diff(no_sim)
     assert np.all(~same | (d < 0) | ((d == 0) & (np.diff(no_ids) > 0)))
+
+
+def test_lsh_weighted_host_inputs_int64_validated():
+    # weighted SimHash with every input on the host, 64-bit offsets and the
+    # CSR and weight checks switched on
+    g = graph("dense")
+    k = 128
+    gauss, _ = draws(g, scan.COSINE, k, 77)
+    w = graphgen.edge_weights(g, 78)
+    oix = oracle.build_index_lsh(g, scan.COSINE, k, gauss, None, w, threads=8)
+    say("weighted SimHash, host inputs, int64, validated")
+    off = g.off.astype(np.int64)
+    gix = scan.scan_build_index_lsh(off, g.adj.astype(np.int32), scan.WEIGHTED_COSINE, k, gauss, None, w,
+                                    FLAGS | scan.SCAN_VALIDATE)
+    assert_same(gix, oix)

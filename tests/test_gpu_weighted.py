@@ -203,3 +203,11 @@ def test_weighted_rmat20_sampled():
     same = rows[1:] == rows[:-1]
     d = np.diff(no_sim)
     assert np.all(~same | (d < 0) | ((d == 0) & (np.diff(no_ids) > 0)))
+
+
+def test_weighted_validated_build():
+    # SCAN_VALIDATE on a valid graph with finite weights changes nothing
+    g = graphgen.rmat(11, 8, seed=40)
+    w = graphgen.edge_weights(g, 41)
+    say("weighted validated build")
+    assert_weighted_equal(weighted_gpu(g, w, flags=FLAGS | scan.SCAN_VALIDATE), oracle.build_index_weighted(g, w))
