@@ -5,10 +5,34 @@ Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 The arithmetic lives in ``scan_oracle.cpp`` (plain C++17, no fast-math,
 ``-ffp-contract=off``); this module only marshals numpy arrays.
 
-Parity status: every function here is pinned by the CPU tests
-(``tests/test_oracle_*.py``) against hand-worked graphs, closed forms,
-invariants and a brute-force direct SCAN written separately from the
-definitions of Section 3.1; none is "parity unpinned".
+Parity status: each function below is pinned by the CPU tests named beside
+it, against hand-worked graphs, closed forms, invariants or a brute-force
+direct SCAN written separately from the definitions of Section 3.1; none is
+"parity unpinned".
+
+  validate                       test_oracle_pins: test_validate
+  similarities, edge_similarity  test_oracle_pins: hand-worked, closed forms,
+                                 trace(A^3), dense counts, brute force
+  edge_similarities              test_oracle_pins:
+                                 test_edge_similarities_equal_full_pass
+  neighbor_order(_row), core_order, build_index
+                                 test_oracle_pins: hand-worked orders and
+                                 invariants; the one-row order equals the pass
+  query                          test_oracle_pins: direct SCAN at every
+                                 (mu, eps) breakpoint, hand-worked, Figure 1
+  roles, modularity              test_oracle_pins: Figure 1, hand-worked
+                                 fixture; closed forms, exact rational sums
+  weighted_*                     test_oracle_weighted (the per-edge function:
+                                 test_weighted_edge_function_equals_full_pass)
+  simhash_/minhash_sketches      test_oracle_lsh: hand-worked sketches
+  lsh_similarities               test_oracle_lsh: exact below the thresholds,
+                                 twins, unbiasedness, hand-worked estimates
+  lsh_edge_similarities          test_oracle_lsh: test_edge_function_equals_
+                                 full_pass (every slot, SimHash, weighted
+                                 SimHash, MinHash) and the hand-worked
+                                 approximated edges
+  build_index_lsh                test_oracle_lsh:
+                                 test_build_index_lsh_composes_the_orders
 """
 
 from __future__ import annotations
@@ -112,8 +136,15 @@ class OracleIndex:
 
 
 def validate(g) -> int:
-    """-1 if g is a valid simple undirected CSR, else the first bad row."""
+    """-1 if g is a valid simple undirected CSR, else the first bad row. Rows
+    must lie inside adj and the last one must end at its end."""
     off, adj = _csr(g)
+    if g.n > 0:
+        past = np.nonzero(off[1:] > len(adj))[0]
+        if len(past):
+            return int(past[0])
+        if int(off[-1]) != len(adj):
+            return g.n - 1
     bad = ctypes.c_int64(-1)
     rc = _load().oracle_validate(g.n, _p(off), _p(adj), ctypes.byref(bad))
     return -1 if rc == 0 else int(bad.value)
@@ -261,15 +292,44 @@ def minhash_sketches(g, k: int, perm: np.ndarray, vs) -> np.ndarray:
     return out
 
 
+def _lsh_inputs(g, kind: int, k: int, gauss, perm, w):
+    """Checks and marshals the LSH draws: the cosine kinds (COSINE, and
+    WEIGHTED_COSINE, which needs w) take SimHash directions gauss (n x k), JACCARD
+    a permutation perm of 0..n-1; w has one weight per CSR slot. Returns
+    (gauss flat or None, perm or None, w or None)."""
+    if kind not in (COSINE, JACCARD, WEIGHTED_COSINE):
+        raise ValueError(f"unknown similarity kind {kind}")
+    if k < 1:
+        raise ValueError("k must be >= 1")
+    if kind == WEIGHTED_COSINE and w is None:
+        raise ValueError("WEIGHTED_COSINE needs the edge weights w")
+    if kind == JACCARD and w is not None:
+        raise ValueError("weights go with the cosine kinds only")
+    gp = pp = None
+    if kind == JACCARD:
+        if perm is None:
+            raise ValueError("MinHash (JACCARD) needs the permutation perm")
+        pp = np.ascontiguousarray(perm, dtype=np.uint32)
+        if pp.shape != (g.n,) or (g.n and int(pp.max()) >= g.n):
+            raise ValueError("perm must hold n values in [0, n)")
+    else:
+        if gauss is None:
+            raise ValueError("SimHash (the cosine kinds) needs the Gaussian draws gauss")
+        gp = np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1)
+        if gp.size != g.n * k:
+            raise ValueError(f"gauss must hold n * k = {g.n * k} values")
+    ww = None if w is None else _weights(g, w)
+    return gp, pp, ww
+
+
 def lsh_similarities(g, kind: int, k: int, gauss=None, perm=None, w=None, threads: int = 1) -> np.ndarray:
     """Per-slot approximate similarities (Section 5 + the Section 6.3 heuristic):
-    kind COSINE uses SimHash with `gauss` (n x k), weighted when w is given;
-    kind JACCARD uses k-partition MinHash with `perm`."""
+    the cosine kinds use SimHash with `gauss` (n x k), weighted when w is given
+    (required for WEIGHTED_COSINE); JACCARD uses k-partition MinHash with
+    `perm`."""
+    gp, pp, ww = _lsh_inputs(g, kind, k, gauss, perm, w)
     off, adj = _csr(g)
     sim = np.zeros(g.nnz, np.float64)
-    gp = None if gauss is None else np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1)
-    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
-    ww = None if w is None else _weights(g, w)
     _load().oracle_lsh_similarities(g.n, _p(off), _p(adj), None if ww is None else _p(ww), kind, k,
                                     None if gp is None else _p(gp), None if pp is None else _p(pp), threads,
                                     _p(sim))
@@ -277,11 +337,10 @@ def lsh_similarities(g, kind: int, k: int, gauss=None, perm=None, w=None, thread
 
 
 def lsh_edge_similarities(g, kind: int, k: int, us, vs, gauss=None, perm=None, w=None) -> np.ndarray:
-    """lsh_similarities at the given edges only (sampled checks)."""
+    """lsh_similarities at the given edges only (sampled checks on large
+    graphs): each edge's sketches are recomputed from the draws."""
+    gp, pp, ww = _lsh_inputs(g, kind, k, gauss, perm, w)
     off, adj = _csr(g)
-    gp = None if gauss is None else np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1)
-    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
-    ww = None if w is None else _weights(g, w)
     lib = _load()
     args = (g.n, _p(off), _p(adj), None if ww is None else _p(ww), kind, k, None if gp is None else _p(gp),
             None if pp is None else _p(pp))

@@ -214,9 +214,10 @@ double minhash_estimate(const std::vector<uint32_t> &a, const std::vector<uint32
 }
 
 // Section 6.3's heuristic: a vertex is high degree when its degree exceeds k
-// (cosine) or 3k/2 (Jaccard); only edges between two such vertices are
-// approximated.
-bool lsh_high(int32_t kind, int64_t deg, int64_t k) { return kind == 0 ? deg > k : 2 * deg > 3 * k; }
+// (the cosine kinds, 0 and 2: SimHash) or 3k/2 (Jaccard, kind 1: MinHash);
+// only edges between two such vertices are approximated.
+bool lsh_jaccard(int32_t kind) { return kind == 1; }
+bool lsh_high(int32_t kind, int64_t deg, int64_t k) { return lsh_jaccard(kind) ? 2 * deg > 3 * k : deg > k; }
 
 // Sort key for both orders: similarity descending, then vertex id ascending.
 struct Entry {
@@ -238,8 +239,10 @@ extern "C" {
 int oracle_validate(int64_t n, const int64_t *off, const int32_t *adj, int64_t *bad_vertex) {
   *bad_vertex = -1;
   if (n < 0 || off[0] != 0) return -2;
-  for (int64_t v = 0; v < n; ++v) {
+  // every row range first, so that the symmetry search below reads valid rows
+  for (int64_t v = 0; v < n; ++v)
     if (off[v + 1] < off[v]) { *bad_vertex = v; return -2; }
+  for (int64_t v = 0; v < n; ++v) {
     for (int64_t s = off[v]; s < off[v + 1]; ++s) {
       int64_t w = adj[s];
       bool ok = w >= 0 && w < n && w != v && (s == off[v] || adj[s - 1] < w);
@@ -340,7 +343,7 @@ void oracle_lsh_similarities(int64_t n, const int64_t *off, const int32_t *adj, 
   std::vector<std::vector<uint32_t>> mh(n);
   parallel_for_dynamic(n, threads, [&](int64_t v) {
     if (!lsh_high(kind, degree(off, v), k)) return;
-    if (kind == 0) sbits[v] = simhash_sketch(off, adj, w, k, gauss, v);
+    if (!lsh_jaccard(kind)) sbits[v] = simhash_sketch(off, adj, w, k, gauss, v);
     else mh[v] = minhash_sketch(off, adj, n, k, perm, v);
   });
   parallel_for_dynamic(n, threads, [&](int64_t u) {
@@ -349,17 +352,17 @@ void oracle_lsh_similarities(int64_t n, const int64_t *off, const int32_t *adj, 
       if (v < u) continue;
       double x;
       if (lsh_high(kind, degree(off, u), k) && lsh_high(kind, degree(off, v), k)) {
-        if (kind == 0) {
+        if (!lsh_jaccard(kind)) {
           int64_t h = 0;
           for (int64_t i = 0; i < k; ++i) h += sbits[u][i] != sbits[v][i];
           x = simhash_estimate(h, k);
         } else {
           x = minhash_estimate(mh[u], mh[v]);
         }
-      } else if (kind == 0 && w) {
+      } else if (!lsh_jaccard(kind) && w) {
         x = weighted_cosine(off, adj, w, u, v);
       } else {
-        x = similarity(kind, common_open_neighbours(off, adj, u, v) + 2, degree(off, u) + 1, degree(off, v) + 1);
+        x = similarity(lsh_jaccard(kind) ? 1 : 0, common_open_neighbours(off, adj, u, v) + 2, degree(off, u) + 1, degree(off, v) + 1);
       }
       int64_t m = std::lower_bound(adj + off[v], adj + off[v + 1], (int32_t)u) - adj;
       sim[s] = x;
@@ -372,7 +375,7 @@ void oracle_lsh_similarities(int64_t n, const int64_t *off, const int32_t *adj, 
 double oracle_lsh_edge_similarity(int64_t n, const int64_t *off, const int32_t *adj, const double *w, int32_t kind,
                                   int64_t k, const double *gauss, const uint32_t *perm, int64_t u, int64_t v) {
   if (lsh_high(kind, degree(off, u), k) && lsh_high(kind, degree(off, v), k)) {
-    if (kind == 0) {
+    if (!lsh_jaccard(kind)) {
       const auto a = simhash_sketch(off, adj, w, k, gauss, u), b = simhash_sketch(off, adj, w, k, gauss, v);
       int64_t h = 0;
       for (int64_t i = 0; i < k; ++i) h += a[i] != b[i];
@@ -380,8 +383,8 @@ double oracle_lsh_edge_similarity(int64_t n, const int64_t *off, const int32_t *
     }
     return minhash_estimate(minhash_sketch(off, adj, n, k, perm, u), minhash_sketch(off, adj, n, k, perm, v));
   }
-  if (kind == 0 && w) return weighted_cosine(off, adj, w, u, v);
-  return similarity(kind, common_open_neighbours(off, adj, u, v) + 2, degree(off, u) + 1, degree(off, v) + 1);
+  if (!lsh_jaccard(kind) && w) return weighted_cosine(off, adj, w, u, v);
+  return similarity(lsh_jaccard(kind) ? 1 : 0, common_open_neighbours(off, adj, u, v) + 2, degree(off, u) + 1, degree(off, v) + 1);
 }
 
 // Algorithm 2, MakeNeighborOrder: each row sorted by non-increasing

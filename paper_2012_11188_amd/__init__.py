@@ -303,12 +303,19 @@ def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None, 
     return Index(out.value, s)
 
 
+def _numel(a) -> int:
+    return int(a.numel()) if hasattr(a, "numel") else int(np.asarray(a).size)
+
+
 def scan_build_index_weighted(off, adj, weights, flags: int = 0, stream=None) -> Index:
     """Builds the index under Section 3.1's weighted cosine; weights (float64,
     one per CSR slot, parallel to adj) live where the graph does: a GPU
-    tensor with GPU tensors, a numpy array with numpy arrays."""
-    lib = _ready()
+    tensor with GPU tensors, a numpy array with numpy arrays. A weight count
+    other than nnz raises ValueError before anything runs."""
     c, keep = _csr_struct(off, adj)
+    if weights is None or _numel(weights) != c.nnz:
+        raise ValueError(f"weights must have nnz = {c.nnz} entries")
+    lib = _ready()
     if c.on_device:
         import torch
         if not (isinstance(weights, torch.Tensor) and weights.is_cuda and weights.dtype == torch.float64):
@@ -318,8 +325,6 @@ def scan_build_index_weighted(off, adj, weights, flags: int = 0, stream=None) ->
     else:
         weights = np.ascontiguousarray(weights, dtype=np.float64)
         ptr = weights.ctypes.data if weights.size else None
-    if (weights.numel() if hasattr(weights, "numel") else weights.size) != c.nnz:
-        raise ValueError(f"weights must have nnz = {c.nnz} entries")
     s = _stream_handle(stream)
     out = ctypes.c_void_p()
     _check(lib.scan_build_index_weighted(ctypes.byref(c), ctypes.c_void_p(ptr), int(flags), ctypes.c_void_p(s),
@@ -342,14 +347,39 @@ def _side_ptr(a, on_device, dtype_np, dtype_name):
     return (a.ctypes.data if a.size else None), a
 
 
+def _check_lsh_inputs(n: int, nnz: int, kind: int, samples: int, gauss, perm, weights):
+    """The draw and weight arrays must have exactly the sizes the kernels
+    read: gauss n x samples (cosine kinds), perm n (Jaccard), weights nnz
+    (weighted cosine). Raises ValueError otherwise, before any device work."""
+    if kind in (COSINE, WEIGHTED_COSINE):
+        if gauss is None or _numel(gauss) != n * int(samples):
+            raise ValueError(f"SimHash needs gauss with n * samples = {n * int(samples)} values")
+        if perm is not None:
+            raise ValueError("perm goes with JACCARD only")
+    elif kind == JACCARD:
+        if perm is None or _numel(perm) != n:
+            raise ValueError(f"MinHash needs perm with n = {n} values")
+        if gauss is not None:
+            raise ValueError("gauss goes with the cosine kinds only")
+    else:
+        raise ValueError(f"unknown similarity kind {kind}")
+    if kind == WEIGHTED_COSINE:
+        if weights is None or _numel(weights) != nnz:
+            raise ValueError(f"WEIGHTED_COSINE needs weights with nnz = {nnz} values")
+    elif weights is not None:
+        raise ValueError("weights go with WEIGHTED_COSINE only")
+
+
 def scan_build_index_lsh(off, adj, kind: int, samples: int, gauss=None, perm=None, weights=None, flags: int = 0,
                          stream=None) -> Index:
     """Approximate index (Section 5 with Section 6.3's heuristic): SimHash for
     COSINE / WEIGHTED_COSINE (gauss: n x samples float64 draws; weights for
     the weighted kind), k-partition MinHash for JACCARD (perm: uint32
-    permutation of 0..n-1). Inputs live where the graph lives."""
-    lib = _ready()
+    permutation of 0..n-1). Inputs live where the graph lives; arrays of any
+    other size raise ValueError before anything runs."""
     c, keep = _csr_struct(off, adj)
+    _check_lsh_inputs(int(c.n), int(c.nnz), int(kind), samples, gauss, perm, weights)
+    lib = _ready()
     pg, kg = _side_ptr(gauss, c.on_device, np.float64, "float64")
     pp, kp = _side_ptr(perm, c.on_device, np.uint32, "uint32")
     pw, kw = _side_ptr(weights, c.on_device, np.float64, "float64")

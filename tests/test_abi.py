@@ -91,3 +91,37 @@ def test_product_path_has_no_cpu_fallback():
     assert "oracle" not in src.replace("no CPU fallback", "")
     for f in os.listdir(os.path.join(ROOT, "paper_2012_11188_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2012_11188_amd", "csrc", f)).read()
+
+
+def _tiny_host_graph():
+    import numpy as np
+
+    # path 0 - 1 - 2 on the host
+    return np.array([0, 1, 3, 4], np.int32), np.array([1, 0, 2, 1], np.int32)
+
+
+@pytest.mark.parametrize("kind,kw,needle", [
+    (scan.COSINE, {"gauss": [0.0] * 5}, "n * samples"),                 # 3 x 64 expected
+    (scan.COSINE, {}, "n * samples"),                                   # no draws
+    (scan.COSINE, {"gauss": [0.0] * 192, "perm": [0, 1, 2]}, "JACCARD only"),
+    (scan.JACCARD, {"perm": [0, 1]}, "n = 3"),                          # short permutation
+    (scan.JACCARD, {"perm": [0, 1, 2], "gauss": [0.0] * 192}, "cosine kinds only"),
+    (scan.WEIGHTED_COSINE, {"gauss": [0.0] * 192, "weights": [1.0] * 3}, "nnz = 4"),
+    (scan.WEIGHTED_COSINE, {"gauss": [0.0] * 192}, "nnz = 4"),           # no weights
+    (scan.COSINE, {"gauss": [0.0] * 192, "weights": [1.0] * 4}, "WEIGHTED_COSINE only"),
+    (9, {"gauss": [0.0] * 192}, "unknown similarity kind"),
+])
+def test_lsh_binding_rejects_wrong_sizes_before_device_work(kind, kw, needle):
+    # raised by the binding before the library or the GPU is touched: an
+    # undersized draw array would otherwise be read out of bounds
+    off, adj = _tiny_host_graph()
+    with pytest.raises(ValueError, match=re.escape(needle)):
+        scan.scan_build_index_lsh(off, adj, kind, 64, **kw)
+
+
+def test_weighted_binding_rejects_wrong_sizes_before_device_work():
+    off, adj = _tiny_host_graph()
+    with pytest.raises(ValueError, match="nnz = 4"):
+        scan.scan_build_index_weighted(off, adj, [1.0, 1.0, 1.0])
+    with pytest.raises(ValueError, match="nnz = 4"):
+        scan.scan_build_index_weighted(off, adj, None)

@@ -113,3 +113,130 @@ def test_minhash_unbiased_jaccard():
     sd = math.sqrt(jac * (1 - jac) / 40 / seeds)  # at least ~40 of the 64 bins are occupied here
     assert abs(np.mean(est) - jac) < 4 * sd
     assert all(0 <= x <= 1 for x in est)
+
+
+# --------------------------------------------------------------------------
+# The per-edge entry point (the checker of sampled GPU parity on large
+# graphs) against the full pass, and both against hand-worked estimates.
+
+
+def two_stars(d: int):
+    """u = 0 joined to 1..d-1 and to the leaves 2..d, v = 1 joined to 0 and to
+    d+1..2d-1: deg(0) = deg(1) = d; N[0] = {0..d}, N[1] = {0, 1, d+1..2d-1};
+    n = 2d. Only the edge {0, 1} joins two vertices of degree d."""
+    e = [(0, 1)] + [(0, x) for x in range(2, d + 1)] + [(1, x) for x in range(d + 1, 2 * d)]
+    return graphgen.from_edges(2 * d, e)
+
+
+def test_simhash_approximated_edge_hand_worked():
+    # k = 4 directions, d = 5 > k: {0, 1} is approximated, every other edge
+    # (a leaf, degree 1) is exact. N[0] = {0..5}, N[1] = {0, 1, 6..9}.
+    #   direction 0: all +1                      -> both dots 6        -> 1, 1
+    #   direction 1: -1 on 2..5, +1/2 elsewhere  -> N[0]: 1 - 4 = -3    -> 0
+    #                                               N[1]: 6 * 1/2 = 3   -> 1
+    #   direction 2: all -1                      -> both -6            -> 0, 0
+    #   direction 3: all 0                       -> both 0 (>= 0)      -> 1, 1
+    # h = 1 differing bit: the estimate is cos(pi / 4).
+    g = two_stars(5)
+    gauss = np.zeros((10, 4))
+    gauss[:, 0] = 1.0
+    gauss[:, 1] = 0.5
+    gauss[2:6, 1] = -1.0
+    gauss[:, 2] = -1.0
+    assert oracle.simhash_sketches(g, 4, gauss, [0, 1]).tolist() == [[1, 0, 0, 1], [1, 1, 0, 1]]
+    want = math.cos(math.pi / 4)
+    full = oracle.lsh_similarities(g, oracle.COSINE, 4, gauss=gauss)
+    s01, s10 = int(g.off[0]), int(g.off[1])  # slots (0, 1) and (1, 0)
+    assert full[s01] == want and full[s10] == want
+    assert oracle.lsh_edge_similarities(g, oracle.COSINE, 4, [0, 1], [1, 0], gauss=gauss).tolist() == [want, want]
+    # the leaf edges keep their exact cosine: c = 2, a = 6 and 2
+    leaf = oracle.lsh_edge_similarities(g, oracle.COSINE, 4, [0], [2], gauss=gauss)[0]
+    assert leaf == 2 / math.sqrt(12) and full[int(g.off[0]) + 1] == leaf
+    # weighted, w(0, 1) = w(1, 0) = 2: direction 1 gives N[0]: 1/2 + 2/2 - 4 =
+    # -2.5 -> 0 and N[1]: 2/2 + 1/2 + 2 = 3.5 -> 1; the other bits are unchanged
+    w = np.ones(g.nnz)
+    w[s01] = w[s10] = 2.0
+    for kind in (oracle.COSINE, oracle.WEIGHTED_COSINE):
+        fw = oracle.lsh_similarities(g, kind, 4, gauss=gauss, w=w)
+        assert fw[s01] == want
+        assert oracle.lsh_edge_similarities(g, kind, 4, [1], [0], gauss=gauss, w=w)[0] == want
+
+
+def test_minhash_approximated_edge_hand_worked():
+    # k = 4 bins, d = 7 > 3k/2 = 6: {0, 1} is approximated. n = 14, perm = the
+    # identity, bin(x) = floor(4x / 14): x 0..3 -> 0, 4..6 -> 1, 7..10 -> 2,
+    # 11..13 -> 3. N[0] = {0..7} -> [0, 4, 7, E]; N[1] = {0, 1, 8..13} ->
+    # [0, E, 8, 11]. One match (bin 0), no bin empty in both: 1/4.
+    E = 0xFFFFFFFF
+    g = two_stars(7)
+    perm = np.arange(14, dtype=np.uint32)
+    assert oracle.minhash_sketches(g, 4, perm, [0, 1]).tolist() == [[0, 4, 7, E], [0, E, 8, 11]]
+    full = oracle.lsh_similarities(g, oracle.JACCARD, 4, perm=perm)
+    assert full[int(g.off[0])] == 0.25 and full[int(g.off[1])] == 0.25
+    assert oracle.lsh_edge_similarities(g, oracle.JACCARD, 4, [0, 1], [1, 0], perm=perm).tolist() == [0.25, 0.25]
+    # a leaf edge keeps the exact Jaccard: c = 2, a = 8 and 2 -> 2 / 8
+    assert oracle.lsh_edge_similarities(g, oracle.JACCARD, 4, [0], [3], perm=perm)[0] == 0.25
+    assert full[int(g.off[0]) + 2] == 0.25
+
+
+LSH_CASES = [("simhash", oracle.COSINE, False), ("simhash_weighted", oracle.COSINE, True),
+             ("simhash_weighted_kind", oracle.WEIGHTED_COSINE, True), ("minhash", oracle.JACCARD, False)]
+
+
+@pytest.mark.parametrize("name,kind,weighted", LSH_CASES)
+@pytest.mark.parametrize("gname", ["rmat10", "rmat11"])
+def test_edge_function_equals_full_pass(name, kind, weighted, gname):
+    # Every slot of graphs holding both approximated edges (two endpoints above
+    # the threshold) and exact ones: the per-edge function must return the
+    # full pass's value bit for bit.
+    if gname == "rmat10":
+        g, k = graphgen.rmat(10, 8, seed=6), 64
+    else:
+        g, k = graphgen.rmat(11, 16, seed=8), 128
+    gauss = graphgen.gaussians(g.n, k, 31) if kind != oracle.JACCARD else None
+    perm = graphgen.permutation(g.n, 31) if kind == oracle.JACCARD else None
+    w = graphgen.edge_weights(g, 32) if weighted else None
+    full = oracle.lsh_similarities(g, kind, k, gauss, perm, w, threads=4)
+    rows = np.repeat(np.arange(g.n), np.diff(g.off))
+    per_edge = oracle.lsh_edge_similarities(g, kind, k, rows, g.adj, gauss, perm, w)
+    assert np.array_equal(full.view(np.uint64), per_edge.view(np.uint64))
+    deg = np.diff(g.off)
+    thr = (lambda d: 2 * d > 3 * k) if kind == oracle.JACCARD else (lambda d: d > k)
+    approx = thr(deg[rows]) & thr(deg[g.adj])
+    assert approx.any() and (~approx).any()  # both kinds of edges are covered
+    # the exact edges equal the exact index of the same kind
+    exact = (oracle.weighted_similarities(g, w) if weighted
+             else oracle.similarities(g, oracle.JACCARD if kind == oracle.JACCARD else oracle.COSINE)[1])
+    assert np.array_equal(full[~approx].view(np.uint64), exact[~approx].view(np.uint64))
+
+
+def test_lsh_inputs_rejected():
+    g = two_stars(5)
+    gauss = np.zeros((10, 4))
+    with pytest.raises(ValueError):
+        oracle.lsh_similarities(g, 7, 4, gauss=gauss)  # unknown kind
+    with pytest.raises(ValueError):
+        oracle.lsh_similarities(g, oracle.WEIGHTED_COSINE, 4, gauss=gauss)  # no weights
+    with pytest.raises(ValueError):
+        oracle.lsh_edge_similarities(g, oracle.COSINE, 4, [0], [1], gauss=gauss[:9])  # short draws
+    with pytest.raises(ValueError):
+        oracle.lsh_similarities(g, oracle.JACCARD, 4)  # no permutation
+    with pytest.raises(ValueError):
+        oracle.lsh_similarities(g, oracle.JACCARD, 4, perm=np.full(10, 10, np.uint32))  # values >= n
+
+
+def test_build_index_lsh_composes_the_orders():
+    # the approximate index is Algorithm 2's orders over the LSH similarities
+    g, k = graphgen.rmat(10, 8, seed=6), 64
+    perm = graphgen.permutation(g.n, 9)
+    ix = oracle.build_index_lsh(g, oracle.JACCARD, k, perm=perm)
+    sim = oracle.lsh_similarities(g, oracle.JACCARD, k, perm=perm)
+    assert np.array_equal(ix.sim.view(np.uint64), sim.view(np.uint64))
+    no_ids, no_sim = oracle.neighbor_order(g, sim)
+    assert np.array_equal(ix.no_ids, no_ids) and np.array_equal(ix.no_sim.view(np.uint64), no_sim.view(np.uint64))
+    co_off, co_ids, co_thr = oracle.core_order(g, no_sim, ix.dmax)
+    assert np.array_equal(ix.co_off, co_off) and np.array_equal(ix.co_ids, co_ids)
+    for v in range(0, g.n, 97):
+        a, b = int(g.off[v]), int(g.off[v + 1])
+        ids, sims = oracle.neighbor_order_row(g.adj[a:b], sim[a:b])
+        assert np.array_equal(ids, ix.no_ids[a:b])

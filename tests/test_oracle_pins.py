@@ -224,6 +224,20 @@ def test_validate():
     assert oracle.validate(loop) == 0
     unsorted = graphgen.Graph(3, np.array([0, 2, 3, 4]), np.array([2, 1, 0, 0], np.int32))
     assert oracle.validate(unsorted) == 0
+    # a repeated id in a row (0 lists 1 twice; 1 lists 0 twice): not strictly ascending
+    dup = graphgen.Graph(2, np.array([0, 2, 4]), np.array([1, 1, 0, 0], np.int32))
+    assert oracle.validate(dup) == 0
+    # repeated only in row 1: row 0 is fine, row 1 is the first bad one
+    dup1 = graphgen.Graph(3, np.array([0, 1, 3, 4]), np.array([1, 0, 0, 1], np.int32))
+    assert oracle.validate(dup1) == 1
+    # ids past n - 1 and negative ids
+    high = graphgen.Graph(3, np.array([0, 0, 1, 1]), np.array([3], np.int32))
+    assert oracle.validate(high) == 1
+    neg = graphgen.Graph(3, np.array([0, 0, 1, 1]), np.array([-1], np.int32))
+    assert oracle.validate(neg) == 1
+    # offsets that decrease (row 1 would be [2, 1))
+    dec = graphgen.Graph(3, np.array([0, 2, 1, 2]), np.array([1, 2], np.int32))
+    assert oracle.validate(dec) == 1
 
 
 # --------------------------------------------------------------------------
@@ -440,3 +454,25 @@ def test_modularity_matches_the_printed_sum(seed):
     exact = modularity_by_definition(g, memb)
     assert (Fraction(s_in) - Fraction(sd2, g.nnz)) / g.nnz == exact
     assert abs(Fraction(q) - exact) <= Fraction(4 * 2 ** -52) * max(1, abs(exact))
+
+
+# --------------------------------------------------------------------------
+# The per-edge entry points (checkers of sampled parity on graphs too large
+# for the full oracle pass) against the full pass, every slot.
+
+
+@pytest.mark.parametrize("kind", [oracle.COSINE, oracle.JACCARD])
+@pytest.mark.parametrize("gi", range(3))
+def test_edge_similarities_equal_full_pass(gi, kind):
+    g = invariant_graphs()[gi]
+    counts, sim = oracle.similarities(g, kind, threads=4)
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    c, s = oracle.edge_similarities(g, rows, g.adj.astype(np.int64), kind)
+    assert np.array_equal(c, counts)
+    assert np.array_equal(s.view(np.uint64), sim.view(np.uint64))
+    # the one-row order of a row's per-edge similarities is the full pass's row
+    ix = oracle.build_index(g, kind)
+    for v in range(0, g.n, max(1, g.n // 40)):
+        a, b = int(g.off[v]), int(g.off[v + 1])
+        ids, sims = oracle.neighbor_order_row(g.adj[a:b], s[a:b])
+        assert np.array_equal(ids, ix.no_ids[a:b]) and np.array_equal(sims.view(np.uint64), ix.no_sim[a:b].view(np.uint64))
