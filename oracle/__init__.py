@@ -78,6 +78,10 @@ def _load():
     lib.oracle_similarities.restype = None
     lib.oracle_edge_similarity.argtypes = [vp, vp, i32, i64, i64, vp]
     lib.oracle_edge_similarity.restype = f64
+    lib.oracle_edge_similarities.argtypes = [vp, vp, i32, i64, vp, vp, i32, vp, vp]
+    lib.oracle_edge_similarities.restype = None
+    lib.oracle_hardware_concurrency.argtypes = []
+    lib.oracle_hardware_concurrency.restype = i32
     lib.oracle_neighbor_order.argtypes = [i64, vp, vp, vp, i32, vp, vp]
     lib.oracle_neighbor_order.restype = None
     lib.oracle_neighbor_order_row.argtypes = [i64, vp, vp, vp, vp]
@@ -168,16 +172,35 @@ def edge_similarity(g, u: int, v: int, kind: int = COSINE):
     return int(c.value), float(s)
 
 
-def edge_similarities(g, us: np.ndarray, vs: np.ndarray, kind: int = COSINE):
+def hardware_concurrency() -> int:
+    """std::thread::hardware_concurrency() of this host."""
+    return int(_load().oracle_hardware_concurrency())
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def edge_similarities(g, us: np.ndarray, vs: np.ndarray, kind: int = COSINE, threads: int = 1):
+    """(counts c, similarities) of the edges (us[i], vs[i]), each computed
+    alone by oracle_edge_similarity, spread over `threads`."""
     off, adj = _csr(g)
-    lib = _load()
-    c = ctypes.c_int32()
+    us = np.ascontiguousarray(us, dtype=np.int64)
+    vs = np.ascontiguousarray(vs, dtype=np.int64)
+    if us.shape != vs.shape:
+        raise ValueError("us and vs differ in length")
+    if len(us) and (min(us.min(), vs.min()) < 0 or max(us.max(), vs.max()) >= g.n):
+        raise ValueError("edge endpoints must be vertices of g")
     cs = np.zeros(len(us), np.int32)
     ss = np.zeros(len(us), np.float64)
-    po, pa = _p(off), _p(adj)
-    for i, (u, v) in enumerate(zip(us.tolist(), vs.tolist())):
-        ss[i] = lib.oracle_edge_similarity(po, pa, kind, u, v, ctypes.byref(c))
-        cs[i] = c.value
+    _load().oracle_edge_similarities(_p(off), _p(adj), kind, len(us), _p(us), _p(vs), threads, _p(cs), _p(ss))
     return cs, ss
 
 

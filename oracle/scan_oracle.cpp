@@ -289,6 +289,20 @@ double oracle_edge_similarity(const int64_t *off, const int32_t *adj, int32_t ki
   return similarity(kind, c, degree(off, u) + 1, degree(off, v) + 1);
 }
 
+// Hardware threads the host reports (std::thread::hardware_concurrency), for
+// stating how many cores a timing used.
+int32_t oracle_hardware_concurrency() { return (int32_t)std::thread::hardware_concurrency(); }
+
+// oracle_edge_similarity over a list of edges (us[i], vs[i]), spread over
+// threads: sampled checks of graphs too large for the full pass.
+void oracle_edge_similarities(const int64_t *off, const int32_t *adj, int32_t kind, int64_t count,
+                              const int64_t *us, const int64_t *vs, int32_t threads, int32_t *counts,
+                              double *sims) {
+  parallel_for_dynamic(count, threads, [&](int64_t i) {
+    sims[i] = oracle_edge_similarity(off, adj, kind, us[i], vs[i], &counts[i]);
+  });
+}
+
 // Algorithm 1 (weighted cosine): every undirected edge {u, v}, u < v, gets
 // its similarity in both CSR slots. w is parallel to adj.
 void oracle_weighted_similarities(int64_t n, const int64_t *off, const int32_t *adj, const double *w,

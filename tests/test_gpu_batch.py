@@ -90,3 +90,36 @@ def test_batch_errors_and_free_order():
     m = scan.scan_query(ixs[1], 2, 0.5)
     torch.cuda.synchronize()
     assert np.array_equal(m.cpu().numpy(), oracle.query(oracle.build_index(g), 2, 0.5)[0])
+
+
+@pytest.mark.timeout(900)
+def test_sbm256_full_config_every_graph():
+    """The batched-build workload itself: 256 uneven SBM graphs (n log-uniform
+    in [1e3, 2e5], 5-200 blocks, average degree 8-64, p_out / p_in = 0.02),
+    built in one merged build; every graph's index equals the oracle's, bit for
+    bit, and two queries per graph equal the oracle's."""
+    import os
+    import time
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    t = time.time()
+    gs = graphgen.batch_sbm(256)
+    print(f"256 graphs, sum nnz {sum(g.nnz for g in gs)}, generated in {time.time() - t:.1f}s", flush=True)
+    dev = [device_csr(g, 64) for g in gs]
+    t = time.time()
+    ixs = scan.scan_build_index_batch(dev, scan.COSINE, scan.SCAN_KEEP_SIMS | scan.SCAN_KEEP_COUNTS)
+    torch.cuda.synchronize()
+    print(f"merged build {time.time() - t:.2f}s", flush=True)
+    del dev
+    threads = min(16, os.cpu_count() or 1)
+    t = time.time()
+    with ThreadPoolExecutor(threads) as ex:  # the oracle's C calls release the GIL
+        futs = [ex.submit(oracle.build_index, g, oracle.COSINE, 1) for g in gs]
+        for i, (g, ix, f) in enumerate(zip(gs, ixs, futs)):
+            oix = f.result()
+            assert_index_equal(ix, oix, g)
+            assert_queries_equal(ix, oix, [(5, 0.6), (3, 0.3)])
+            if i % 32 == 31:
+                print(f"graphs 0..{i} equal ({time.time() - t:.1f}s)", flush=True)

@@ -467,7 +467,7 @@ def test_edge_similarities_equal_full_pass(gi, kind):
     g = invariant_graphs()[gi]
     counts, sim = oracle.similarities(g, kind, threads=4)
     rows = np.repeat(np.arange(g.n), g.degrees())
-    c, s = oracle.edge_similarities(g, rows, g.adj.astype(np.int64), kind)
+    c, s = oracle.edge_similarities(g, rows, g.adj.astype(np.int64), kind, threads=4)
     assert np.array_equal(c, counts)
     assert np.array_equal(s.view(np.uint64), sim.view(np.uint64))
     # the one-row order of a row's per-edge similarities is the full pass's row
