@@ -46,20 +46,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def byte_model(st: dict, split: dict, s_off: int) -> dict:
-    """Algorithmic bytes, fixed before measurement. Build: CSR read once, the
-    min-side intersection work W_min (each shorter-row id read, 4 B, plus one
-    4 B probe), similarities written once per slot, neighbour order read and
-    written, core order read and written:
-        s_off(n+1) + 56 nnz + 8 W_min.
-    The bitmap-owner kernel alone: 8 W + 16 E over the edges it owns (W their
-    min-side work, E their count; each result goes to both CSR slots)."""
+def byte_model(st: dict, split: dict, s_off: int, deg=None, small_max: int = 256) -> dict:
+    """Algorithmic bytes, fixed before measurement.
+
+    Build, the survey's model (labelled "model" in the output): CSR read once,
+    the min-side intersection work W_min charged 8 B per id (the shorter
+    row's id, 4 B, and one 4 B probe of the longer row), similarities
+    written once per slot, neighbour order read and written, core order read
+    and written: s_off(n+1) + 56 nnz + 8 W_min.
+
+    Build, memory model (what must cross the memory interface in this
+    design): the same less the probe half, 4 W_min, since the longer row is
+    probed in an LDS bitmap or hash table, on chip: s_off(n+1) + 56 nnz +
+    4 W_min.
+
+    Owner kernels, memory model: every lower neighbour's row streamed once per
+    owned edge (4 B per id: 4 W), every owner slot staged once (its id, the
+    neighbour's degree and offset: 16 B per slot of an owner of that class),
+    both similarity slots of every owned edge written (16 B per edge). The
+    survey's 8 W + 16 E is kept beside it."""
     n, nnz, wmin = st["n"], st["nnz"], st["w_min"]
+    s_big = s_small = 0
+    if deg is not None:
+        s_big = int(deg[deg > small_max].sum())
+        s_small = int(deg[deg <= small_max].sum())
     return {
-        "build": s_off * (n + 1) + 56 * nnz + 8 * wmin,
+        "build_model": s_off * (n + 1) + 56 * nnz + 8 * wmin,
+        "build": s_off * (n + 1) + 56 * nnz + 4 * wmin,
         "floor": s_off * (n + 1) + 28 * nnz,
-        "k_big_owner": 8 * split["w_big"] + 16 * split["edges_big"],
-        "k_small_owner": 8 * split["w_small"] + 16 * split["edges_small"],
+        "k_big_owner_model": 8 * split["w_big"] + 16 * split["edges_big"],
+        "k_big_owner": 4 * split["w_big"] + 16 * s_big + 16 * split["edges_big"],
+        "k_small_owner_model": 8 * split["w_small"] + 16 * split["edges_small"],
+        "k_small_owner": 4 * split["w_small"] + 16 * s_small + 16 * split["edges_small"],
     }
 
 
@@ -149,13 +167,32 @@ def autotune(scan, graphs, kind, tune_arg, reps=2):
 
 
 def kernel_roofline(bm, phases, tune, workload):
+    """Roofline of the dominant kernel, k_big_owner: achieved = its
+    memory-model bytes per launch / its hipEvent duration; traffic = the
+    measured bytes between L2 and memory per launch (rocprofv3 counters,
+    calibrated); model_frac = the survey's 8 W + 16 E model, whose probe half
+    is served from LDS (so it may exceed 1)."""
     big_ms = phases["intersect_big_ms"]
-    achieved = bm["k_big_owner"] / (big_ms * 1e-3) / 1e9
+    sec = big_ms * 1e-3
+    achieved = bm["k_big_owner"] / sec / 1e9
     traffic, why = counter_traffic(tune, workload)
     return {"bound": "hbm", "kernel": "k_big_owner", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": why,
-            "bytes_per_launch": bm["k_big_owner"], "launch_ms": big_ms,
+            "traffic_frac": (traffic / sec / 1e9 / HBM_PEAK_GBS) if traffic else None,
+            "bytes_per_launch": bm["k_big_owner"],
+            "bytes_model": "4 B per streamed lower-row id + 16 B per owner slot + 16 B per owned edge",
+            "launch_ms": big_ms,
+            "model_bytes_per_launch": bm["k_big_owner_model"],
+            "model_frac": bm["k_big_owner_model"] / sec / 1e9 / HBM_PEAK_GBS,
             "traffic_over_algorithmic": (traffic / bm["k_big_owner"]) if traffic else None}
+
+
+def build_roofline(bm, total_ms):
+    sec = total_ms * 1e-3
+    return {"bytes": bm["build"], "achieved": bm["build"] / sec / 1e9, "frac": bm["build"] / sec / 1e9 / HBM_PEAK_GBS,
+            "bytes_model": "s_off(n+1) + 56 nnz + 4 W_min (intersection probes are on-chip)",
+            "model_bytes": bm["build_model"], "model_frac": bm["build_model"] / sec / 1e9 / HBM_PEAK_GBS,
+            "floor_bytes": bm["floor"], "floor_frac": bm["floor"] / sec / 1e9 / HBM_PEAK_GBS}
 
 
 # ---------------------------------------------------------------------------
@@ -243,9 +280,38 @@ def serving(scan, torch, ix, n, args):
     return res
 
 
+def query_bytes(scan, ix, mus, epss):
+    """Per-query algorithmic bytes, B_q(mu, eps) = 4 K + 24 sum over the K
+    cores u of (p_u + 1) + 8 n: the core ids, each core's eps-prefix of its
+    neighbour order (ids, similarities and the neighbours' core tests) and the
+    per-vertex state read and memberships written; p_u = the length of u's
+    eps-prefix. Evaluated on the host from the exported index."""
+    off = scan.scan_index_export(ix, scan.ARR_OFFSETS)
+    no_sim = scan.scan_index_export(ix, scan.ARR_NO_SIM)
+    co_off = scan.scan_index_export(ix, scan.ARR_CO_OFF)
+    co_ids = scan.scan_index_export(ix, scan.ARR_CO_IDS)
+    co_thr = scan.scan_index_export(ix, scan.ARR_CO_THR)
+    n, dmax = ix.info.n, ix.info.dmax
+    prefix = {}
+    out = []
+    for mu, eps in zip(mus, epss):
+        mu, eps = int(mu), float(eps)
+        if eps not in prefix:
+            c = np.concatenate([[0], np.cumsum(no_sim >= eps)])
+            prefix[eps] = c[off[1:]] - c[off[:-1]]
+        K, z = 0, 0
+        if mu <= dmax + 1:
+            b, e = co_off[mu], co_off[mu + 1]
+            K = int(np.searchsorted(-co_thr[b:e], -eps, side="right"))
+            z = int((prefix[eps][co_ids[b:b + K]] + 1).sum())
+        out.append(4 * K + 24 * z + 8 * n)
+    return np.array(out, np.int64)
+
+
 def closed_loop_queries(scan, torch, ix, n, queries, B):
     """mu ~ U{2..16}, eps ~ U{0.10, ..., 0.90}: synchronous one at a time vs
-    scan_query_batch of B."""
+    scan_query_batch of B; each query's bytes B_q and the rate they imply at
+    its one-at-a-time latency."""
     rng = np.random.default_rng(7)
     q_mu = rng.integers(2, 17, queries)
     q_eps = np.array([(10 + 5 * k) / 100.0 for k in rng.integers(0, 17, queries)])
@@ -267,7 +333,16 @@ def closed_loop_queries(scan, torch, ix, n, queries, B):
         torch.cuda.synchronize()
         batched += [(time.perf_counter() - t) * 1e3] * len(q_mu[i:i + B])
     tb = time.perf_counter() - tb0
+    bq = query_bytes(scan, ix, q_mu, q_eps)
+    rate = bq / (np.array(single) * 1e-3) / 1e9
+    per_query = [{"mu": int(m), "eps": float(e), "bytes": int(b), "ms": float(t), "gbs": float(r)}
+                 for m, e, b, t, r in zip(q_mu, q_eps, bq, single, rate)]
     return {"queries": queries, "batch": B,
+            "bytes_model": "B_q = 4 K + 24 sum_cores (p_u + 1) + 8 n",
+            "bytes_per_query": {"p50": float(np.percentile(bq, 50)), "min": int(bq.min()), "max": int(bq.max()),
+                                "gbs_at_one_at_a_time_p50": float(np.percentile(rate, 50)),
+                                "gbs_at_one_at_a_time_max": float(rate.max())},
+            "per_query": per_query,
             "one_at_a_time": {"p50_ms": float(np.percentile(single, 50)), "p99_ms": float(np.percentile(single, 99)),
                               "qps": queries / (sum(single) / 1e3)},
             "batched": {"p50_ms": float(np.percentile(batched, 50)), "p99_ms": float(np.percentile(batched, 99)),
@@ -378,9 +453,10 @@ def lsh_timing(scan, torch, graphgen, g, off, adj, exact_ms, steps, k=256):
 
 def sweep_timing(scan, torch, ix, dmax, batch=32):
     """Section 7.3.4's parameter selection on the index: the modularity of
-    every (mu, eps) of the paper's grid (mu = 2..2^18 in powers of two up to
-    dmax + 1, eps = .01 .. .99), as batched queries plus device modularity."""
-    grid = scan.paper_sweep_grid(dmax)
+    every (mu, eps) of the paper's grid Sigma (mu = 2, 4, ..., 2^18 by 99
+    eps = .01 .. .99: 1,782 cells), as batched queries plus device modularity.
+    Cells with mu > dmax + 1 have no cores: every vertex is a singleton."""
+    grid = scan.paper_sweep_grid()
     mus = np.array([m for m, _ in grid], np.int32)
     epss = np.array([e for _, e in grid])
     scan.scan_sweep_modularity(ix, mus[:batch], epss[:batch], batch=batch)  # warm
@@ -389,8 +465,85 @@ def sweep_timing(scan, torch, ix, dmax, batch=32):
     q = scan.scan_sweep_modularity(ix, mus, epss, batch=batch)
     wall = time.perf_counter() - t
     best = int(np.argmax(q))
-    return {"queries": len(grid), "batch": batch, "wall_s": wall, "queries_per_s": len(grid) / wall,
+    return {"queries": len(grid), "cells_mu_above_dmax_plus_1": int((mus > dmax + 1).sum()), "batch": batch,
+            "wall_s": wall, "queries_per_s": len(grid) / wall,
             "best": {"mu": int(mus[best]), "eps": float(epss[best]), "modularity": float(q[best])}}
+
+
+# ---------------------------------------------------------------------------
+# Quality of approximate clusterings (Section 7.3.4)
+
+
+def _labels(m):
+    """Unclustered vertices (-1) as singletons: label n + v."""
+    m = np.asarray(m, np.int64)
+    return np.where(m >= 0, m, len(m) + np.arange(len(m)))
+
+
+def adjusted_rand_index(a, b) -> float:
+    """Section 7.2's adjusted Rand index of two clusterings (membership
+    arrays, -1 = unclustered = a cluster of its own), from the contingency
+    counts n_ij and their row and column sums, in exact integers up to the
+    last division."""
+    la, lb = _labels(a), _labels(b)
+    n = len(la)
+    if n < 2:
+        return 1.0
+
+    def pairs(cnt):
+        cnt = cnt.astype(object)
+        return int(sum(c * (c - 1) // 2 for c in cnt))
+
+    _, ia = np.unique(la, return_inverse=True)
+    _, ib = np.unique(lb, return_inverse=True)
+    _, nij = np.unique(ia.astype(np.int64) * (ib.max() + 1) + ib, return_counts=True)
+    sij, si, sj = pairs(nij), pairs(np.bincount(ia)), pairs(np.bincount(ib))
+    total = n * (n - 1) // 2
+    expected = si * sj / total
+    top = 0.5 * (si + sj) - expected
+    return 1.0 if top == 0 else (sij - expected) / top
+
+
+def best_cell(scan, ix, grid, batch=32):
+    mus = np.array([m for m, _ in grid], np.int32)
+    epss = np.array([e for _, e in grid])
+    q = scan.scan_sweep_modularity(ix, mus, epss, batch=batch)
+    i = int(np.argmax(q))
+    return int(mus[i]), float(epss[i]), float(q[i])
+
+
+def approx_quality(scan, torch, graphgen, name, g, off, adj, k, seeds=5):
+    """For SimHash (cosine) and MinHash (Jaccard) with k samples, over
+    `seeds` draws: the best modularity over Sigma of the approximate index,
+    and the ARI of its clustering against the exact index's clustering at the
+    exact index's best (mu, eps) (Section 7.3.4)."""
+    grid = scan.paper_sweep_grid()
+    deg = np.diff(g.off)
+    out = {"graph": name, "samples": k, "seeds": seeds}
+    for label, kind in (("simhash_cosine", scan.COSINE), ("minhash_jaccard", scan.JACCARD)):
+        hi = deg > k if kind == scan.COSINE else 2 * deg > 3 * k
+        exact = scan.scan_build_index(off, adj, kind, 0)
+        mu, eps, q = best_cell(scan, exact, grid)
+        ref = scan.scan_query(exact, mu, eps).cpu().numpy()
+        rows = []
+        for sd in range(seeds):
+            if kind == scan.COSINE:
+                gauss, perm = torch.from_numpy(graphgen.gaussians(g.n, k, 500 + sd)).cuda(), None
+            else:
+                gauss, perm = None, torch.from_numpy(graphgen.permutation(g.n, 500 + sd)).cuda()
+            ax = scan.scan_build_index_lsh(off, adj, kind, k, gauss, perm, None, 0)
+            amu, aeps, aq = best_cell(scan, ax, grid)
+            am = scan.scan_query(ax, mu, eps).cpu().numpy()
+            rows.append({"seed": 500 + sd, "best_modularity": aq, "best": [amu, aeps],
+                         "ari_at_exact_best": adjusted_rand_index(am, ref)})
+            del ax, gauss, perm
+        out[label] = {"exact_best": {"mu": mu, "eps": eps, "modularity": q,
+                                     "clusters": int(len(np.unique(ref[ref >= 0])))},
+                      "sketched_vertices": int(hi.sum()),
+                      "approx_best_modularity_mean": float(np.mean([r["best_modularity"] for r in rows])),
+                      "ari_mean": float(np.mean([r["ari_at_exact_best"] for r in rows])), "trials": rows}
+        del exact
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -419,7 +572,7 @@ def rmat_workload(args, scan, torch, graphgen):
     kinds = [scan.COSINE] if scale == 20 else [scan.COSINE, scan.JACCARD]
     tune, tinfo = autotune(scan, [(off, adj)], scan.COSINE, args.tune, reps=2 if scale == 20 else 1)
     split = graphgen.owner_split(g, tune["small_max"])
-    bm = byte_model(st, split, s_off)
+    bm = byte_model(st, split, s_off, np.diff(g.off), tune["small_max"])
     results = {}
     for kind in kinds:
         ms, dev_ms, profs, ixs = timed_builds(
@@ -439,11 +592,9 @@ def rmat_workload(args, scan, torch, graphgen):
     extra = {"phases_ms": phases, "device_ms_per_step": dev_ms,
              "tune": dict(tinfo, **tune), "owner_split": split,
              "roofline": kernel_roofline(bm, phases, tune, workload),
-             "build_roofline": {"bytes": bm["build"], "floor_bytes": bm["floor"],
-                                "achieved": bm["build"] / (phases["total_ms"] * 1e-3) / 1e9,
-                                "frac": bm["build"] / (phases["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                "floor_frac": bm["floor"] / (phases["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
-             "k_small_owner": {"bytes": bm["k_small_owner"], "launch_ms": phases["intersect_small_ms"],
+             "build_roofline": build_roofline(bm, phases["total_ms"]),
+             "k_small_owner": {"bytes": bm["k_small_owner"], "model_bytes": bm["k_small_owner_model"],
+                               "launch_ms": phases["intersect_small_ms"],
                                "achieved_gbs": bm["k_small_owner"] / max(phases["intersect_small_ms"], 1e-6) / 1e6}}
     if scan.JACCARD in results:
         jms, jdev, jph, _ = results[scan.JACCARD]
@@ -452,6 +603,14 @@ def rmat_workload(args, scan, torch, graphgen):
     if scale == 20 and not args.no_lsh:
         extra["lsh"] = lsh_timing(scan, torch, graphgen, g, off, adj, ms, args.steps)
         log(f"lsh: {extra['lsh']}")
+        if not args.no_quality:
+            qual = [approx_quality(scan, torch, graphgen, "rmat20", g, off, adj, 256)]
+            s2 = graphgen.sbm2000()
+            o2 = torch.from_numpy(s2.off.astype(np.int32)).cuda()
+            a2 = torch.from_numpy(s2.adj).cuda()
+            qual.append(approx_quality(scan, torch, graphgen, "sbm2000", s2, o2, a2, 64))
+            extra["approx_quality"] = qual
+            log(f"approximate quality: {qual}")
     if scale == 20 and not args.no_weighted:
         extra["weighted"] = weighted_timing(scan, torch, graphgen, g, off, adj, st, args.steps)
         log(f"weighted: {extra['weighted']}")
@@ -466,31 +625,52 @@ def rmat_workload(args, scan, torch, graphgen):
             extra["serving"] = serving(scan, torch, ix, g.n, args)
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        if scale == 20:
-            log(f"cpu baseline: oracle full build on {threads} threads ...")
-            t = time.perf_counter()
-            oracle.build_index(g, oracle.COSINE, threads=threads)
-            tc = time.perf_counter() - t
-            cpu = {"value": g.num_edges / tc, "unit": "edges/s", "cores": threads, "kind": "oracle",
-                   "sample": f"one full cosine index build of the same R-MAT-20 graph (similarities, neighbour "
-                             f"order, core order), {tc:.1f} s"}
-        else:
-            k = 200_000
-            rng = np.random.default_rng(5)
-            slots = rng.integers(0, g.nnz, k)
-            u = np.searchsorted(g.off, slots, side="right") - 1
-            t = time.perf_counter()
-            oracle.edge_similarities(g, u, g.adj[slots].astype(np.int64), oracle.COSINE)
-            tc = time.perf_counter() - t
-            cpu = {"value": k / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
-                   "sample": f"similarity of {k} uniformly sampled edges of the same graph, one thread, "
-                             f"{tc:.1f} s (similarity phase only)"}
+        cpu = rmat_cpu_baseline(args, g, scale)
         log(f"cpu baseline: {cpu}")
     extra["cpu_baseline"] = cpu
     return record(value, args.steps, args.warmup, ms, "f64", config, **extra)
+
+
+def host_info(oracle):
+    return {"cpu_model": oracle.cpu_model(), "hardware_concurrency": oracle.hardware_concurrency(),
+            "os_cpu_count": os.cpu_count()}
+
+
+def rmat_cpu_baseline(args, g, scale):
+    """The oracle on the host cores, untuned: one full cosine build on all
+    cores (R-MAT-20; on R-MAT-23 the similarity of sampled edges, the full
+    build being too slow), and the similarity of uniformly sampled edges on
+    one thread and on all cores (each edge computed alone)."""
+    import oracle
+
+    info = host_info(oracle)
+    threads = args.cpu_threads or info["hardware_concurrency"]
+    rng = np.random.default_rng(5)
+    k = 200_000 if scale == 20 else 100_000
+    slots = rng.integers(0, g.nnz, k)
+    u = np.searchsorted(g.off, slots, side="right") - 1
+    v = g.adj[slots].astype(np.int64)
+    t = time.perf_counter()
+    oracle.edge_similarities(g, u, v, oracle.COSINE, threads=1)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.edge_similarities(g, u, v, oracle.COSINE, threads=threads)
+    tn = time.perf_counter() - t
+    sampled = {"one_thread": {"value": k / t1, "unit": "edges/s", "cores": 1, "seconds": t1},
+               "all_cores": {"value": k / tn, "unit": "edges/s", "cores": threads, "seconds": tn},
+               "sample": f"similarity of {k} uniformly sampled CSR slots of the same graph, each edge alone "
+                         f"(the similarity phase only)"}
+    if scale == 20:
+        log(f"cpu baseline: oracle full build on {threads} threads ...")
+        t = time.perf_counter()
+        oracle.build_index(g, oracle.COSINE, threads=threads)
+        tc = time.perf_counter() - t
+        return dict({"value": g.num_edges / tc, "unit": "edges/s", "cores": threads, "kind": "oracle",
+                     "sample": f"one full cosine index build of the same R-MAT-20 graph (similarities, "
+                               f"neighbour order, core order) on {threads} threads, {tc:.1f} s",
+                     "sampled_similarity": sampled}, **info)
+    return dict({"value": sampled["all_cores"]["value"], "unit": "edges/s", "cores": threads, "kind": "oracle",
+                 "sample": sampled["sample"] + f", on {threads} threads", "sampled_similarity": sampled}, **info)
 
 
 def sbm_batch_workload(args, scan, torch, graphgen):
@@ -523,20 +703,48 @@ def sbm_batch_workload(args, scan, torch, graphgen):
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        info = host_info(oracle)
+        threads = args.cpu_threads or info["hardware_concurrency"]
         sample = gs[:32]
         t = time.perf_counter()
         for g in sample:
             oracle.build_index(g, oracle.COSINE, threads=threads)
         tc = time.perf_counter() - t
-        cpu = {"value": sum(g.num_edges for g in sample) / tc, "unit": "edges/s", "cores": threads,
-               "kind": "oracle", "sample": f"full cosine index builds of the first 32 of the 256 graphs, {tc:.1f} s"}
+        t = time.perf_counter()
+        for g in sample[:8]:
+            oracle.build_index(g, oracle.COSINE, threads=1)
+        t1 = time.perf_counter() - t
+        cpu = dict({"value": sum(g.num_edges for g in sample) / tc, "unit": "edges/s", "cores": threads,
+                    "kind": "oracle",
+                    "sample": f"full cosine index builds of the first 32 of the 256 graphs on {threads} threads, "
+                              f"{tc:.1f} s",
+                    "one_thread": {"value": sum(g.num_edges for g in sample[:8]) / t1, "unit": "edges/s",
+                                   "cores": 1, "sample": f"full builds of the first 8 graphs on one thread, "
+                                                         f"{t1:.1f} s"}}, **info)
         log(f"cpu baseline: {cpu}")
+    # memory-model bytes summed over the graphs (int64 offsets), and the
+    # dominant kernel class of this workload: the small owners
+    bm = {"build": 0, "build_model": 0, "floor": 0, "k_small_owner": 0, "k_small_owner_model": 0,
+          "k_big_owner": 0, "k_big_owner_model": 0}
+    for g in gs:
+        b = byte_model(graphgen.degree_stats(g), graphgen.owner_split(g, tune["small_max"]), 8, np.diff(g.off),
+                       tune["small_max"])
+        for key in bm:
+            bm[key] += b[key]
+    sec = phases["intersect_small_ms"] * 1e-3
+    small_roof = {"bound": "hbm", "kernel": "k_small_owner (both launches)",
+                  "achieved": bm["k_small_owner"] / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": bm["k_small_owner"] / sec / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                  "traffic_source": "not taken for this workload", "bytes_per_launch": bm["k_small_owner"],
+                  "bytes_model": "4 B per streamed lower-row id + 16 B per owner slot + 16 B per owned edge",
+                  "launch_ms": phases["intersect_small_ms"], "model_bytes_per_launch": bm["k_small_owner_model"],
+                  "model_frac": bm["k_small_owner_model"] / sec / 1e9 / HBM_PEAK_GBS}
     config = {"workload": "sbm256_batched_cosine_index_build", "graphs": 256, "seed": 256,
               "n_range": [1000, 200000], "blocks": [5, 200], "avg_degree": [8, 64], "p_out_over_p_in": 0.02,
               "sum_n": int(sum(g.n for g in gs)), "edges": int(edges), "offsets": "int64", "tune": tune}
     return record(edges / (ms * 1e-3), args.steps, args.warmup, ms, "f64", config,
                   phases_ms=phases, device_ms_per_step=dev_ms, tune=dict(tinfo, **tune),
+                  roofline=small_roof, build_roofline=build_roofline(bm, phases["total_ms"]),
                   sequential={"ms_per_256_builds": seq_ms, "edges_per_s": edges / (seq_ms * 1e-3)},
                   speedup_vs_sequential=seq_ms / ms, cpu_baseline=cpu)
 
@@ -556,6 +764,8 @@ def main():
     ap.add_argument("--no-queries", action="store_true")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-cosine build timing")
     ap.add_argument("--no-lsh", action="store_true", help="skip the approximate (LSH) build timing")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the approximate-vs-exact clustering quality (ARI, best modularity)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -576,12 +786,17 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        # known-size references for the HBM byte counters: a copy (MiB read +
+        # MiB written), a sum (MiB read) and a fill (MiB written) of int32
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"copy calibration: {args.copy_calibration} MiB read + written")
+        total = int(src.sum(dtype=torch.int64).item())
+        dst.fill_(3)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB copied, summed ({total}) and filled")
         del src, dst
     if args.workload == "sbm256":
         rec = sbm_batch_workload(args, scan, torch, graphgen)

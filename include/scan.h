@@ -26,7 +26,8 @@
  *     returns a message for the calling thread. No C++ exception crosses the
  *     ABI. Argument errors are detected before any device work is enqueued.
  *   - Streams: `stream` is a hipStream_t (NULL = the default stream). Device
- *     work is enqueued on it asynchronously unless a function says otherwise.
+ *     work is enqueued on it asynchronously unless a function says otherwise;
+ *     the builds (scan_build_index*) are synchronous, see there.
  *   - Ownership: the caller owns the CSR and every output buffer; the library
  *     never keeps a caller pointer after a call returns. The library owns each
  *     scan_index and scan_server and their device memory until the matching
@@ -142,11 +143,18 @@ typedef void *(*scan_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*scan_release_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
 scan_status scan_set_allocator(scan_alloc_fn alloc, scan_release_fn release, void *ctx);
 
-/* Builds the index of Section 3.2 (Algorithms 1 and 2) for graph g.
- * Enqueues degrees, per-edge intersection + similarity, the neighbour-order
- * segmented sort and the core-order sort on `stream`; *out is usable on
- * `stream` immediately (later work on other streams must wait for it).
- * The CSR must stay valid until the stream reaches the end of the build.
+/* Builds the index of Section 3.2 (Algorithms 1 and 2) for graph g: degrees,
+ * per-edge intersection + similarity, the neighbour-order segmented sort and
+ * the core-order sort, run on `stream`.
+ * Synchronous: the call returns once the build has completed on the device,
+ * and *out is then ready for use on any stream. The host waits on `stream`
+ * while the build runs, to read the maximum degree (it sizes the core-order
+ * tables), the owner work counts (they size the intersection grids), the
+ * size classes of each segmented sort (they size the sort grids) and, at the
+ * end, for the device to finish with the host-side tables; with
+ * SCAN_VALIDATE also for the validation result. Other work already queued on
+ * `stream` is waited for too; builds on different streams therefore run one
+ * after the other. The CSR may be freed once the call returns.
  * Errors: SCAN_EINVAL (null g/out/pointers with n > 0, n < 0, nnz < 0, odd
  * nnz, offset_bits not 32/64, unknown kind or flag, n or nnz too large for
  * int32 ids / the chosen offsets), SCAN_EGRAPH (SCAN_VALIDATE only),
@@ -174,7 +182,8 @@ scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_k
  * fixed FP64 value per edge; with all weights 1 the index equals the
  * SCAN_SIM_COSINE one bit for bit. Neighbour order, core order and queries are
  * as for the other kinds; the index has no intersection counts. The weights
- * must stay valid until the stream reaches the end of the build.
+ * may be freed once the call returns (the build is synchronous, as
+ * scan_build_index).
  * Errors: as scan_build_index, plus SCAN_EINVAL for a null weights pointer
  * with nnz > 0 or SCAN_KEEP_COUNTS, and SCAN_EGRAPH (SCAN_VALIDATE only) for a
  * weight that is not finite. */
@@ -207,8 +216,8 @@ typedef struct {
 
 /* Builds the approximate index of graph g. kind: SCAN_SIM_COSINE or
  * SCAN_SIM_WEIGHTED_COSINE (SimHash, needs gauss) or SCAN_SIM_JACCARD
- * (MinHash, needs perm). The inputs must stay valid until the stream reaches
- * the end of the build. Errors: as scan_build_index, plus SCAN_EINVAL for a
+ * (MinHash, needs perm). Synchronous like scan_build_index: the inputs may be
+ * freed once the call returns. Errors: as scan_build_index, plus SCAN_EINVAL for a
  * null lsh, samples out of range, a missing draw array, weights with another
  * kind or none with SCAN_SIM_WEIGHTED_COSINE, SCAN_KEEP_COUNTS, or a
  * permutation value >= n. */

@@ -120,6 +120,22 @@ def test_lsh_without_high_vertices_is_exact():
                               scan.scan_index_export(b, code).view(np.uint8))
 
 
+def _c_build_lsh(off, adj, kind, samples, gauss=None, perm=None, weights=None, flags=0):
+    """scan_build_index_lsh called through the C ABI directly (no binding
+    checks): returns the status."""
+    import ctypes
+
+    lib = scan.load_library()
+    c, keep = scan._csr_struct(off, adj)
+    ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+    spec = scan._Lsh(int(samples), 0, ptr(gauss), ptr(perm), ptr(weights))
+    out = ctypes.c_void_p()
+    st = lib.scan_build_index_lsh(ctypes.byref(c), int(kind), ctypes.byref(spec), int(flags), None, ctypes.byref(out))
+    if st == scan.SCAN_OK:
+        lib.scan_index_free(out)
+    return st
+
+
 def test_lsh_errors():
     import torch
 
@@ -128,23 +144,24 @@ def test_lsh_errors():
     gauss = torch.from_numpy(graphgen.gaussians(g.n, 64, 1)).cuda()
     perm = torch.from_numpy(graphgen.permutation(g.n, 1)).cuda()
     w = torch.from_numpy(graphgen.edge_weights(g, 1)).cuda()
-    for k in (0, 100, 8192):
+    for k in (0, 100, 8192):  # draws of the matching size: the library rejects k itself
+        gk = torch.zeros(g.n * k, dtype=torch.float64, device="cuda")
         with pytest.raises(scan.ScanError, match="EINVAL"):
-            scan.scan_build_index_lsh(off, adj, scan.COSINE, k, gauss=gauss)
-    with pytest.raises(scan.ScanError, match="EINVAL"):
-        scan.scan_build_index_lsh(off, adj, scan.COSINE, 64, perm=perm)  # SimHash without draws
-    with pytest.raises(scan.ScanError, match="EINVAL"):
-        scan.scan_build_index_lsh(off, adj, scan.JACCARD, 64, gauss=gauss)  # MinHash without perm
-    with pytest.raises(scan.ScanError, match="EINVAL"):
-        scan.scan_build_index_lsh(off, adj, scan.JACCARD, 64, perm=perm, weights=w)
-    with pytest.raises(scan.ScanError, match="EINVAL"):
-        scan.scan_build_index_lsh(off, adj, scan.WEIGHTED_COSINE, 64, gauss=gauss)  # no weights
+            scan.scan_build_index_lsh(off, adj, scan.COSINE, k, gauss=gk)
+    # missing or misplaced draws and weights: the binding refuses them before
+    # the library is called, and the library refuses them too
+    for kind, kw in [(scan.COSINE, {"perm": perm}), (scan.JACCARD, {"gauss": gauss}),
+                     (scan.JACCARD, {"perm": perm, "weights": w}), (scan.WEIGHTED_COSINE, {"gauss": gauss})]:
+        with pytest.raises(ValueError):
+            scan.scan_build_index_lsh(off, adj, kind, 64, **kw)
+        assert _c_build_lsh(off, adj, kind, 64, **kw) == scan.SCAN_EINVAL
     with pytest.raises(scan.ScanError, match="EINVAL"):
         scan.scan_build_index_lsh(off, adj, scan.COSINE, 64, gauss=gauss, flags=scan.SCAN_KEEP_COUNTS)
     bad = perm.clone()
     bad[3] = g.n
     with pytest.raises(scan.ScanError, match="EINVAL"):
         scan.scan_build_index_lsh(off, adj, scan.JACCARD, 64, perm=bad)
+    assert _c_build_lsh(off, adj, scan.COSINE, 64, gauss=gauss) == scan.SCAN_OK
 
 
 @pytest.mark.parametrize("kind", [scan.COSINE, scan.JACCARD])

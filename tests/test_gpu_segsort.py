@@ -98,3 +98,43 @@ def test_segsort_negative_keys():
     ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
     eko, eio = expected(seg_off, keys, ids)
     assert np.array_equal(ko, eko) and np.array_equal(io, eio)
+
+
+def test_segsort_partitioned_long_segments():
+    # segments long enough for hundreds to thousands of buckets (the bucket
+    # count is capped at 4096, so the 9M segment has buckets of ~2.2k), next
+    # to short ones, with few distinct keys (ties broken by id across buckets)
+    lengths = [3, 300_000, 64, 1_000_003, 5000, 1, 9_000_000, 4097]
+    for distinct in (7, 10**6):
+        seg_off, keys, ids = make(lengths, seed=distinct + 1, distinct_keys=distinct)
+        ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
+        wk, wi = expected(seg_off, keys, ids)
+        assert np.array_equal(io, wi), distinct
+        assert np.array_equal(bits(ko), bits(wk)), distinct
+
+
+def test_segsort_partition_with_skewed_samples():
+    # every sampled position of a 100,000-element segment holds the smallest
+    # key, so every splitter does too: all other elements fall into the first
+    # bucket, far over 4096, which must then be sorted by the merge path
+    n, S = 100_000, 16 * ((100_000 + 2047) // 2048)
+    rng = np.random.default_rng(4)
+    keys = 0.6 + 0.4 * rng.random(n)
+    pos = ((2 * np.arange(S) + 1) * n) // (2 * S)
+    keys[pos] = 0.5
+    ids = rng.choice(4 * n, n, replace=False).astype(np.int32)
+    seg_off = np.array([0, 7, 7 + n, 7 + n + 5], np.int64)
+    keys = np.concatenate([rng.random(7) + 0.1, keys, rng.random(5) + 0.1])
+    ids = np.concatenate([np.arange(7, dtype=np.int32), ids, np.arange(5, dtype=np.int32)])
+    ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
+    wk, wi = expected(seg_off, keys, ids)
+    assert np.array_equal(io, wi) and np.array_equal(bits(ko), bits(wk))
+
+
+def test_segsort_all_keys_equal():
+    # one key everywhere: the order is the id order alone, in every class
+    lengths = [1, 40, 900, 4096, 4097, 70_000, 250_000]
+    seg_off, keys, ids = make(lengths, seed=12, distinct_keys=1)
+    ko, io = scan.scan_segmented_sort(seg_off, keys, ids)
+    wk, wi = expected(seg_off, keys, ids)
+    assert np.array_equal(io, wi) and np.array_equal(bits(ko), bits(wk))
