@@ -278,6 +278,26 @@ scan_status scan_query(const scan_index *ix, int32_t mu, double eps, int32_t *me
 scan_status scan_query_ex(const scan_index *ix, int32_t mu, double eps, int32_t *memberships,
                           uint8_t *is_core, int32_t out_on_device, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the query of
+ * scan_query_ex with device outputs, whose workspace (union-find parents,
+ * state bytes and the query descriptor, 5 * n + 256 bytes) lives in a
+ * file-scope device array of the library (40 MiB + 256 bytes, held on each
+ * device the library runs on until the process ends) instead of allocated
+ * memory. It calls no allocator and never waits for the device.
+ * memberships: DEVICE int32[n]; is_core: DEVICE uint8[n] or NULL. Work is
+ * enqueued on `stream` (NULL = the default stream) and the call returns at
+ * once. Every call on one device shares that array: calls that overlap in
+ * time on one device (other streams, other threads) race and their results
+ * are undefined; calls ordered on one stream are safe. Each call clears the
+ * state bytes it uses with a kernel (no memset node), so a result does not
+ * depend on earlier calls.
+ * Errors: SCAN_EINVAL for a null index or memberships, mu < 2, NaN eps, or an
+ * index of more than 2^23 vertices; SCAN_EDEVICE if the array's address
+ * cannot be taken or a launch fails. */
+scan_status scan_query_noalloc(const scan_index *ix, int32_t mu, double eps, int32_t *memberships,
+                               uint8_t *is_core, void *stream);
+
 /* `count` queries (mu[i], eps[i]) answered together in shared launches:
  * memberships is int32[count * n], query i writing [i*n, (i+1)*n). mu and eps
  * are HOST arrays. out_on_device as in scan_query_ex. Each result is identical

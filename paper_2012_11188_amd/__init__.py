@@ -87,7 +87,7 @@ EXPORTS = [
     "scan_server_submit_ex", "scan_server_poll", "scan_server_wait", "scan_server_destroy", "scan_last_error",
     "scan_version", "scan_similarity_values", "scan_index_build_profile", "scan_build_index_ex",
     "scan_autotune", "scan_segmented_sort", "scan_query_roles", "scan_query_modularity",
-    "scan_sweep_modularity",
+    "scan_sweep_modularity", "scan_query_noalloc",
 ]
 
 _lib = None
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
         "scan_query": ([vp, i32, f64, vp], i32),
         "scan_query_ex": ([vp, i32, f64, vp, vp, i32, vp], i32),
         "scan_query_batch": ([vp, i32, vp, vp, vp, i32, vp], i32),
+        "scan_query_noalloc": ([vp, i32, f64, vp, vp, vp], i32),
         "scan_query_roles": ([vp, vp, vp, vp], i32),
         "scan_query_modularity": ([vp, vp, P(f64), vp], i32),
         "scan_sweep_modularity": ([vp, i32, vp, vp, i32, vp, vp], i32),
@@ -503,6 +504,26 @@ def scan_query_ex(ix: Index, mu: int, eps: float, memberships=None, is_core=None
         mp, cp = memberships.ctypes.data, is_core.ctypes.data
     _check(lib.scan_query_ex(ix._h, int(mu), float(eps), ctypes.c_void_p(mp if ix.n else 0),
                              ctypes.c_void_p(cp if ix.n else 0), int(out_on_device), ctypes.c_void_p(s)))
+    return memberships, is_core
+
+
+def scan_query_noalloc(ix: Index, mu: int, eps: float, memberships, is_core=None, stream=None):
+    """(mu, eps) query into device tensors (int32[n] memberships, optional
+    uint8[n] is_core) with the library's fixed scratch workspace: no device
+    allocation in the call. Asynchronous on `stream`."""
+    torch = _torch()
+    lib = _ready()
+    n = ix.n
+    if not (isinstance(memberships, torch.Tensor) and memberships.is_cuda and memberships.dtype == torch.int32
+            and memberships.numel() == n and memberships.is_contiguous()):
+        raise ValueError("memberships must be a contiguous device int32 tensor of n entries")
+    if is_core is not None and not (isinstance(is_core, torch.Tensor) and is_core.is_cuda
+                                    and is_core.dtype == torch.uint8 and is_core.numel() == n
+                                    and is_core.is_contiguous()):
+        raise ValueError("is_core must be a contiguous device uint8 tensor of n entries")
+    cp = is_core.data_ptr() if (is_core is not None and n) else 0
+    _check(lib.scan_query_noalloc(ix._h, int(mu), float(eps), ctypes.c_void_p(memberships.data_ptr() if n else 0),
+                                  ctypes.c_void_p(cp), ctypes.c_void_p(_stream_handle(stream))))
     return memberships, is_core
 
 

@@ -316,6 +316,13 @@ scan_status scan_query_ex(const scan_index *ix, int32_t mu, double eps, int32_t 
   return query_impl(ix, 1, &mu, &eps, memberships, is_core, out_on_device, (hipStream_t)stream);
 }
 
+scan_status scan_query_noalloc(const scan_index *ix, int32_t mu, double eps, int32_t *memberships,
+                               uint8_t *is_core, void *stream) {
+  SCAN_TRY(check_query(ix, mu, eps));
+  if (!memberships && ix->n > 0) return fail(SCAN_EINVAL, "null memberships");
+  return query_noalloc(ix, mu, eps, memberships, is_core, (hipStream_t)stream);
+}
+
 scan_status scan_query_batch(const scan_index *ix, int32_t count, const int32_t *mu,
                              const double *eps, int32_t *memberships, int32_t out_on_device,
                              void *stream) {

@@ -173,6 +173,10 @@ double modularity_value(int64_t s_in, int64_t sd2, int64_t nnz);
 
 // Hub / outlier roles of the unclustered vertices of one query's memberships.
 void launch_roles(const scan_index *ix, const int32_t *memb, uint8_t *roles, hipStream_t s);
+// One query whose workspace is the library's file-scope scratch array (no
+// allocation); memberships / is_core are device pointers.
+scan_status query_noalloc(const scan_index *ix, int32_t mu, double eps, int32_t *memberships, uint8_t *is_core,
+                          hipStream_t s);
 QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,
                           uint8_t *is_core);
 void free_query_slot(QuerySlot *slot, hipStream_t s);

@@ -25,6 +25,7 @@
 #include <climits>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "index.h"
@@ -305,6 +306,67 @@ void launch_roles(const scan_index *ix, const int32_t *memb, uint8_t *roles, hip
   IndexView v{ix->n, ix->dmax, ix->off, ix->no_ids, ix->no_sim, ix->co_off, ix->co_ids, ix->co_thr};
   k_q_roles<<<grid_for((ix->n + kWave / kRoleGroup - 1) / (kWave / kRoleGroup) * kWave, 256), 256, 0, s>>>(
       v, memb, roles);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free query: the slot workspace and the descriptor live in a
+// file-scope device array instead of allocated memory. Layout: the
+// descriptor, then parent int32[n], then the state bytes uint8[n].
+
+constexpr size_t kNoAllocDescBytes = 256;
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 23;
+constexpr size_t kNoAllocScratchBytes = kNoAllocDescBytes + (size_t)kNoAllocMaxN * 5;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// The device address of `scratch` on each device, taken once per device with
+// that device current (the host-side name of the array is not a device
+// address).
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;
+
+static scan_status scratch_address(int device, unsigned char **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    SCAN_HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) SCAN_HIP_TRY(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(SCAN_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = (unsigned char *)g_scratch_ptr[device];
+  return SCAN_OK;
+}
+
+// Clears the state bytes (the query kernels expect them all zero) and writes
+// the descriptor from kernel arguments: no host copy, no memset node.
+__global__ void k_q_noalloc_init(QueryDesc *d, int32_t mu, double eps, int32_t *parent, uint8_t *flag,
+                                 int64_t n, int32_t *memb, uint8_t *is_core) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flag[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d = QueryDesc{mu, 0, eps, 0, 0, parent, flag, memb, is_core};
+}
+
+scan_status query_noalloc(const scan_index *ix, int32_t mu, double eps, int32_t *memberships, uint8_t *is_core,
+                          hipStream_t s) {
+  if (ix->n > kNoAllocMaxN)
+    return fail(SCAN_EINVAL, "scan_query_noalloc takes indexes of at most %lld vertices (this one has %lld)",
+                (long long)kNoAllocMaxN, (long long)ix->n);
+  unsigned char *base;
+  SCAN_TRY(scratch_address(ix->device, &base));
+  if (ix->n == 0) return SCAN_OK;
+  QueryDesc *d = (QueryDesc *)base;
+  int32_t *parent = (int32_t *)(base + kNoAllocDescBytes);
+  uint8_t *flag = (uint8_t *)(parent + ix->n);
+  k_q_noalloc_init<<<grid_for(ix->n, 256, 2048), 256, 0, s>>>(d, mu, eps, parent, flag, ix->n, memberships,
+                                                               is_core);
+  launch_query_kernels(ix, d, 1, s);
+  SCAN_HIP_TRY(hipGetLastError());
+  return SCAN_OK;
 }
 
 QueryDesc make_query_desc(int32_t mu, double eps, const QuerySlot &slot, int32_t *memb,
