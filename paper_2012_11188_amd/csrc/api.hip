@@ -70,6 +70,59 @@ void dev_free(void *p, size_t bytes, hipStream_t stream) {
   (void)hipFreeAsync(p, stream);
 }
 
+static std::mutex g_pinned_mu;
+static std::vector<void *> g_pinned_free;
+
+void *pinned_get() {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      void *p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  void *p = nullptr;
+  if (hipHostMalloc(&p, kPinnedBlock, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pinned_put(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned_free.push_back(p);
+}
+
+static std::mutex g_helper_mu;
+static std::vector<hipStream_t> g_helper;  // kHelpers per device
+
+hipStream_t helper_stream(int k) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_helper_mu);
+  const size_t at = (size_t)dev * kHelpers + (size_t)k;
+  if (g_helper.size() <= at) g_helper.resize((size_t)(dev + 1) * kHelpers, nullptr);
+  if (!g_helper[at] && hipStreamCreateWithFlags(&g_helper[at], hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    g_helper[at] = nullptr;
+  }
+  return g_helper[at];
+}
+
+scan_status stream_wait(hipStream_t waiter, hipStream_t signaller) {
+  if (waiter == signaller) return SCAN_OK;
+  hipEvent_t e;
+  SCAN_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipError_t r = hipEventRecord(e, signaller);
+  if (r == hipSuccess) r = hipStreamWaitEvent(waiter, e, 0);
+  (void)hipEventDestroy(e);
+  if (r != hipSuccess) return fail(SCAN_EDEVICE, "stream ordering failed: %s", hipGetErrorString(r));
+  return SCAN_OK;
+}
+
 }  // namespace scan
 
 using namespace scan;
@@ -441,8 +494,8 @@ scan_status scan_index_build_profile(const scan_index *ix, scan_build_profile *o
   for (int k = 1; k < 6; ++k) SCAN_HIP_TRY(hipEventElapsedTime(&t[k], ev[k - 1], ev[k]));
   float total = 0, small = 0, big = 0;
   SCAN_HIP_TRY(hipEventElapsedTime(&total, ev[0], ev[5]));
-  SCAN_HIP_TRY(hipEventElapsedTime(&small, ev[2], ev[6]));
-  SCAN_HIP_TRY(hipEventElapsedTime(&big, ev[6], ev[3]));
+  SCAN_HIP_TRY(hipEventElapsedTime(&small, ev[6], ev[7]));
+  SCAN_HIP_TRY(hipEventElapsedTime(&big, ev[8], ev[9]));
   out->total_ms = total;
   out->prepare_ms = t[1];
   out->plan_ms = t[2];

@@ -628,6 +628,17 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       if (herr[2 * g])
         return fail(SCAN_EGRAPH, "graph %d is not a simple undirected CSR with ascending rows (first bad row %d)", g, herr[2 * g + 1]);
   }
+  // The neighbour-order segments are the CSR rows: classified by length now,
+  // on a helper stream, so their sizes are on the host when the sort starts.
+  hipStream_t ns = NNZ > 0 ? helper_stream(2) : nullptr;
+  if (ns && stream_wait(ns, s) != SCAN_OK) ns = nullptr;
+  JoinOnExit join_ns{s, ns};
+  SortClasses no_cls;
+  if (NNZ > 0) SCAN_TRY(sort_classify(off_u, N, tmp, ns ? ns : s, no_cls));
+  // a2: the ownership plan needs only the degrees; its counts come back with
+  // the maximum degrees below.
+  IntersectPlan plan;
+  if (NNZ > 0 && !weighted) SCAN_TRY(intersect_plan(cfg, N, NNZ, deg, tmp, s, plan));
   const double *w_dev = weights;  // edge weights on the device (weighted cosine)
   if (weighted && NNZ > 0) {
     if (!gs[0].on_device) {
@@ -726,92 +737,109 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   SCAN_TRY(arena_alloc(*arena, &d_corel, cobase[G]));
 
   if (NNZ > 0) {
+    // a6, first part: core-order sizes and offsets (from the degree
+    // histograms, on the device) and the degree-rank list. These read only the
+    // degrees, so they run on a helper stream while the intersection runs;
+    // the host enqueues them once the intersection kernels are launched.
+    hipStream_t cs = helper_stream(2);
+    if (!cs) cs = s;
+    JoinOnExit join_cs{s, cs};
+    int32_t *d_hist, *d_cursor, *d_sv, *d_tiles_of;
+    int64_t *d_E, *d_seg, *d_nz, *d_tile_first, *scan_ws;
+    double *co_key;
+    int32_t *co_id;
+    SortClasses co_cls;
+    const int64_t nrt = (int64_t)rt.size();
+    auto co_prep = [&]() -> scan_status {  // cs is ordered after the degrees
+      SCAN_TRY(tmp.alloc(&d_hist, hbase[G]));
+      SCAN_TRY(tmp.alloc(&d_cursor, hbase[G]));
+      SCAN_TRY(tmp.alloc(&d_E, Ebase[G]));
+      SCAN_TRY(tmp.alloc(&d_seg, segbase[G] + 1));
+      SCAN_TRY(tmp.alloc(&d_nz, G));
+      SCAN_TRY(tmp.alloc(&d_sv, std::max<int64_t>(N, 1)));
+      SCAN_TRY(tmp.alloc(&d_tiles_of, std::max<int64_t>(nrt, 1)));
+      SCAN_TRY(tmp.alloc(&d_tile_first, nrt + 1));
+      SCAN_TRY(tmp.alloc(&scan_ws, scan_workspace_elems(std::max<int64_t>(nrt, 1))));
+      SCAN_TRY(tmp.alloc(&co_key, NNZ));
+      SCAN_TRY(tmp.alloc(&co_id, NNZ));
+      SCAN_HIP_TRY(hipMemsetAsync(d_hist, 0, (size_t)hbase[G] * 4, cs));
+      SCAN_HIP_TRY(hipMemsetAsync(d_cursor, 0, (size_t)hbase[G] * 4, cs));
+      if (!vt.empty())
+        k_graph_hist<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, cs>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
+                                                                           d_dmax, d_hist);
+      {
+        int64_t *P, *X, *XS, *ws;
+        SCAN_TRY(tmp.alloc(&P, hbase[G] + 1));
+        SCAN_TRY(tmp.alloc(&X, std::max<int64_t>(segbase[G], 1)));
+        SCAN_TRY(tmp.alloc(&XS, segbase[G] + 1));
+        SCAN_TRY(tmp.alloc(&ws, scan_workspace_elems(std::max<int64_t>(hbase[G], segbase[G]))));
+        SCAN_TRY(exclusive_scan(d_hist, P, hbase[G], ws, cs));
+        k_co_counts<<<grid_for(Ebase[G], 256), 256, 0, cs>>>(P, d_hbase, d_Ebase, d_segbase, d_ng, G, d_E, X);
+        SCAN_TRY(exclusive_scan64(X, XS, segbase[G], ws, cs));
+        k_co_offsets<<<grid_for(cobase[G], 256), 256, 0, cs>>>(XS, d_cobase, d_segbase, d_ebase, d_hbase, d_hist, d_ng,
+                                                              G, d_corel, d_seg, d_nz);
+      }
+      if (!vt.empty())
+        k_co_rank<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, cs>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
+                                                                       d_Ebase, d_dmax, d_E, d_cursor, d_ng, d_vbase,
+                                                                       d_sv);
+      if (nrt > 0) {
+        k_co_tiles<<<grid_for(nrt, 256), 256, 0, cs>>>(d_rt, nrt, d_sv, d_vbase, d_nz, deg, d_tiles_of);
+        SCAN_TRY(exclusive_scan(d_tiles_of, d_tile_first, nrt, scan_ws, cs));
+      }
+      return sort_classify(d_seg, segbase[G], tmp, cs, co_cls);  // the core-order segments
+    };
+
     // a2-a4: ownership plan, intersection and similarity over the union.
     IntersectStats ist;
     if (prof) {
-      ist.ev_start = prof->ev[2];
-      ist.ev_mid = prof->ev[6];
-      ist.ev_end = prof->ev[3];
+      ist.ev_small_begin = prof->ev[6];
+      ist.ev_small_end = prof->ev[7];
+      ist.ev_big_begin = prof->ev[8];
+      ist.ev_big_end = prof->ev[9];
+      ist.ev_plan_end = prof->ev[2];
       ist.host_counts = prof->plan_counts;
     }
-    hipEvent_t ev_end = ist.ev_end;
     IntersectConfig icfg = cfg;
-    if (lsh) {  // the edges between two high-degree vertices are left to the approximate pass
-      ist.ev_end = nullptr;  // recorded after it
+    if (lsh)  // the edges between two high-degree vertices are left to the approximate pass
       icfg.skip_deg = kind == SCAN_SIM_JACCARD ? 3 * lsh->samples / 2 : lsh->samples;
+    if (weighted) {
+      mark(2);  // no ownership plan
+      if (cs != s) SCAN_TRY(stream_wait(cs, s));
+      SCAN_TRY(co_prep());
+      SCAN_TRY(weighted_similarity_all(N, NNZ, off_u, deg, adj_u, w_dev, sims, tmp, s, prof ? &ist : nullptr,
+                                       icfg.skip_deg));
+    } else {
+      SCAN_TRY(intersect_all(icfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist, cs, co_prep,
+                             &plan));
     }
-    if (weighted)
-      SCAN_TRY(weighted_similarity_all(N, NNZ, off_u, deg, adj_u, w_dev, sims, tmp, s, ist.ev_start, ist.ev_mid,
-                                       ist.ev_end, icfg.skip_deg));
-    else
-      SCAN_TRY(intersect_all(icfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist));
-    if (lsh) {
-      SCAN_TRY(lsh_overwrite(lsh_dev, N, NNZ, off_u, adj_u, weighted ? w_dev : nullptr, kind, sims, tmp, s));
-      if (ev_end) SCAN_HIP_TRY(hipEventRecord(ev_end, s));
-    }
+    if (lsh) SCAN_TRY(lsh_overwrite(lsh_dev, N, NNZ, off_u, adj_u, weighted ? w_dev : nullptr, kind, sims, tmp, s));
+    mark(3);
     if (prof) {
       prof->window_bits = ist.wbits;
       prof->intersect_launches = ist.launches;
     }
 
     // a5: neighbour order, then ids made local to each graph.
-    SCAN_TRY(segmented_sort(off_u, N, NNZ, sims, adj_u, no_sim, no_ids, s));
+    SCAN_TRY(sort_run(no_cls, off_u, NNZ, sims, adj_u, no_sim, no_ids, s));
     if (G > 1) k_localize_ids<<<grid_for(NNZ, 256), 256, 0, s>>>(no_ids, d_ebase, d_vbase, G, NNZ);
     mark(4);
 
-    // a6: core order: degree histograms, sizes and offsets (device), ranks,
-    // transposed fill, segmented sort.
-    int32_t *d_hist, *d_cursor, *d_sv, *d_tiles_of;
-    int64_t *d_E, *d_seg, *d_nz, *d_tile_first, *scan_ws;
-    double *co_key;
-    int32_t *co_id;
-    const int64_t nrt = (int64_t)rt.size();
-    SCAN_TRY(tmp.alloc(&d_hist, hbase[G]));
-    SCAN_TRY(tmp.alloc(&d_cursor, hbase[G]));
-    SCAN_TRY(tmp.alloc(&d_E, Ebase[G]));
-    SCAN_TRY(tmp.alloc(&d_seg, segbase[G] + 1));
-    SCAN_TRY(tmp.alloc(&d_nz, G));
-    SCAN_TRY(tmp.alloc(&d_sv, std::max<int64_t>(N, 1)));
-    SCAN_TRY(tmp.alloc(&d_tiles_of, std::max<int64_t>(nrt, 1)));
-    SCAN_TRY(tmp.alloc(&d_tile_first, nrt + 1));
-    SCAN_TRY(tmp.alloc(&scan_ws, scan_workspace_elems(std::max<int64_t>(nrt, 1))));
-    SCAN_TRY(tmp.alloc(&co_key, NNZ));
-    SCAN_TRY(tmp.alloc(&co_id, NNZ));
-    SCAN_HIP_TRY(hipMemsetAsync(d_hist, 0, (size_t)hbase[G] * 4, s));
-    SCAN_HIP_TRY(hipMemsetAsync(d_cursor, 0, (size_t)hbase[G] * 4, s));
-    if (!vt.empty())
-      k_graph_hist<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, s>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
-                                                                         d_dmax, d_hist);
-    {
-      int64_t *P, *X, *XS, *ws;
-      SCAN_TRY(tmp.alloc(&P, hbase[G] + 1));
-      SCAN_TRY(tmp.alloc(&X, std::max<int64_t>(segbase[G], 1)));
-      SCAN_TRY(tmp.alloc(&XS, segbase[G] + 1));
-      SCAN_TRY(tmp.alloc(&ws, scan_workspace_elems(std::max<int64_t>(hbase[G], segbase[G]))));
-      SCAN_TRY(exclusive_scan(d_hist, P, hbase[G], ws, s));
-      k_co_counts<<<grid_for(Ebase[G], 256), 256, 0, s>>>(P, d_hbase, d_Ebase, d_segbase, d_ng, G, d_E, X);
-      SCAN_TRY(exclusive_scan64(X, XS, segbase[G], ws, s));
-      k_co_offsets<<<grid_for(cobase[G], 256), 256, 0, s>>>(XS, d_cobase, d_segbase, d_ebase, d_hbase, d_hist, d_ng,
-                                                            G, d_corel, d_seg, d_nz);
-    }
-    if (!vt.empty())
-      k_co_rank<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, s>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
-                                                                     d_Ebase, d_dmax, d_E, d_cursor, d_ng, d_vbase,
-                                                                     d_sv);
+    // a6, second part: transposed fill, segmented sort (after the helper
+    // stream's part above).
+    if (cs != s) SCAN_TRY(stream_wait(s, cs));
     if (nrt > 0) {
-      k_co_tiles<<<grid_for(nrt, 256), 256, 0, s>>>(d_rt, nrt, d_sv, d_vbase, d_nz, deg, d_tiles_of);
-      SCAN_TRY(exclusive_scan(d_tiles_of, d_tile_first, nrt, scan_ws, s));
       k_co_fill<<<grid_for(NNZ / 512 + 1, 1, 1 << 16), 256, 0, s>>>(d_rt, nrt, d_tile_first, d_sv, d_vbase, d_nz,
                                                                     deg, off_u, no_sim, d_corel, d_cobase, d_ebase,
                                                                     d_vbase, co_key, co_id);
     }
-    SCAN_TRY(segmented_sort(d_seg, segbase[G], NNZ, co_key, co_id, co_thr, co_ids, s));
+    SCAN_TRY(sort_run(co_cls, d_seg, NNZ, co_key, co_id, co_thr, co_ids, s));
     SCAN_HIP_TRY(hipGetLastError());
     mark(5);
   } else {
     // no edges: every co_off is zero
     SCAN_HIP_TRY(hipMemsetAsync(d_corel, 0, (size_t)cobase[G] * 8, s));
-    for (int k = 2; k < 7; ++k) mark(k);
+    for (int k = 2; k < 10; ++k) mark(k);
   }
 
   // Per-graph offsets (local), then the index views.

@@ -123,6 +123,25 @@ class DevArena {
   size_t used_ = 0, cap_ = 0;
 };
 
+// Helper streams of the current device (k < kHelpers; default priority,
+// non-blocking), created once per device, for work that may overlap the
+// caller's stream inside one library call: the call forks them from its own
+// stream and joins them back before returning or freeing anything the
+// helper work reads. Null if a stream cannot be created.
+constexpr int kHelpers = 3;
+hipStream_t helper_stream(int k = 0);
+// `waiter` waits for everything enqueued on `signaller` so far.
+scan_status stream_wait(hipStream_t waiter, hipStream_t signaller);
+
+// Joins `helper` into `main` when it goes out of scope (also on early
+// returns), so that stream-ordered frees on `main` come after helper work.
+struct JoinOnExit {
+  hipStream_t main, helper;
+  ~JoinOnExit() {
+    if (helper && helper != main) (void)stream_wait(main, helper);
+  }
+};
+
 // Grid size for grid-stride kernels.
 inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 16) {
   int64_t g = (work + block - 1) / block;
@@ -139,10 +158,40 @@ scan_status exclusive_scan(const int32_t *in, int64_t *out, int64_t n, int64_t *
 scan_status exclusive_scan64(const int64_t *in, int64_t *out, int64_t n, int64_t *ws,
                              hipStream_t s);
 
-// Sorts every segment [seg_off[i], seg_off[i+1]) of (key, id) by key
-// descending, id ascending (ids must be distinct within a segment). Reads
-// key_in/id_in, writes key_out/id_out (may not alias). Waits once for the
-// segment class sizes (they size the grids).
+// Small blocks of pinned host memory (kPinnedBlock bytes each) for values
+// the host reads back from the device while other work runs; reused across
+// calls. Null if pinned memory cannot be had.
+constexpr size_t kPinnedBlock = 4096;
+void *pinned_get();
+void pinned_put(void *p);
+
+// A segmented sort in two steps. sort_classify enqueues, on stream s, the
+// classification of the segments [seg_off[i], seg_off[i+1]) by length (the
+// class lists live in `arena`, which must outlive sort_run) and a copy of the
+// class sizes to pinned host memory. sort_run then waits on the host for
+// those sizes (they size the grids; classified early, they are there before
+// they are needed) and enqueues on s the sort of every segment by key
+// descending, id ascending (ids distinct within a segment), reading
+// key_in/id_in and writing key_out/id_out (no aliasing). s and the stream of
+// sort_classify may differ.
+struct SortClasses {
+  int64_t nseg = 0;
+  int32_t *lists = nullptr;
+  int32_t *big_tiles_of = nullptr;
+  void *stats = nullptr;       // device class sizes
+  void *host = nullptr;        // pinned copy
+  hipEvent_t ready = nullptr;  // recorded after the copy
+  hipStream_t stream = nullptr;
+  SortClasses() = default;
+  SortClasses(const SortClasses &) = delete;
+  SortClasses &operator=(const SortClasses &) = delete;
+  ~SortClasses();
+};
+scan_status sort_classify(const int64_t *seg_off, int64_t nseg, DevArena &arena, hipStream_t s,
+                          SortClasses &c);
+scan_status sort_run(const SortClasses &c, const int64_t *seg_off, int64_t total, const double *key_in,
+                     const int32_t *id_in, double *key_out, int32_t *id_out, hipStream_t s);
+// Both steps on s.
 scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
                            const double *key_in, const int32_t *id_in, double *key_out,
                            int32_t *id_out, hipStream_t s);

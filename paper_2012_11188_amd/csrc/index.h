@@ -1,6 +1,7 @@
 // Index object and internal entry points shared by the library's host code.
 #pragma once
 
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -26,16 +27,44 @@ struct IntersectStats {
   // Optional pinned host int32[4]: receives (light vertices, bitmap chunks,
   // -, heavy vertices) asynchronously, in stream order.
   int32_t *host_counts = nullptr;
-  hipEvent_t ev_start = nullptr;  // recorded after planning, before the first launch
-  hipEvent_t ev_mid = nullptr;    // recorded between the small- and large-owner launches
-  hipEvent_t ev_end = nullptr;    // recorded after the last launch
+  // around the small-owner launches and around the large-owner launch (on
+  // the streams that run them; the two may overlap)
+  hipEvent_t ev_plan_end = nullptr;  // after the ownership plan
+  hipEvent_t ev_small_begin = nullptr, ev_small_end = nullptr;
+  hipEvent_t ev_big_begin = nullptr, ev_big_end = nullptr;
 };
+
+// a2: the ownership plan, enqueued on s (the work lists live in `arena`,
+// which must outlive intersect_all), with a copy of its counts to pinned host
+// memory; intersect_all waits for them on the host. Launched early, the plan
+// is read back by a wait the caller makes anyway.
+struct IntersectPlan {
+  int64_t n = 0, nnz = 0;
+  int32_t *small_list = nullptr, *heavy_list = nullptr;
+  void *big_list = nullptr, *counts = nullptr;  // device chunk list and counts
+  void *host = nullptr;                         // pinned copy of the counts
+  hipEvent_t ready = nullptr;
+  IntersectPlan() = default;
+  IntersectPlan(const IntersectPlan &) = delete;
+  IntersectPlan &operator=(const IntersectPlan &) = delete;
+  ~IntersectPlan();
+};
+scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int32_t *deg,
+                           DevArena &arena, hipStream_t s, IntersectPlan &plan);
 
 // a2-a4: ownership plan, then intersection + similarity for every edge,
 // written into both CSR slots of sims (and counts if non-null).
+// side (may be null): a stream ordered after the plan (for work that needs
+// only what precedes the intersection); after_launch (may be empty) runs on
+// the host once every intersection kernel is enqueued, so that the host
+// enqueues other work while the device intersects. plan (may be null: then
+// it plans on s itself) is one made by intersect_plan on s with the same
+// cfg, n, nnz and deg.
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
                           const int32_t *deg, const int32_t *adj, int kind, double *sims,
-                          int32_t *counts, int device, hipStream_t s, IntersectStats *stats);
+                          int32_t *counts, int device, hipStream_t s, IntersectStats *stats,
+                          hipStream_t side = nullptr, const std::function<scan_status()> &after_launch = {},
+                          const IntersectPlan *plan = nullptr);
 
 // Approximate similarities (lsh.hip): k samples, and the random draws on
 // the device (gauss n x k for SimHash, perm for MinHash).
@@ -47,10 +76,11 @@ struct LshSpec {
 
 // Weighted cosine of every edge into both CSR slots of sims (weighted.hip);
 // events (may be null) before the square sums, before the products, after.
+// The square sums are timed as the "small" part, the owner products as the
+// "big" part (stats may be null).
 scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, const int32_t *deg,
                                     const int32_t *adj, const double *w, double *sims, DevArena &tmp,
-                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end,
-                                    int32_t skip_deg = 0x7fffffff);
+                                    hipStream_t s, const IntersectStats *stats, int32_t skip_deg = 0x7fffffff);
 // Overwrites sims of the edges between two high-degree vertices with their
 // SimHash (cosine kinds) or k-partition MinHash (Jaccard) estimates; w may
 // be null (unweighted). spec's pointers are device pointers.
@@ -98,10 +128,11 @@ struct SharedArena {
 };
 
 // SCAN_PROFILE events of a build (shared by the indexes of a batch): start,
-// prepare, plan, intersect, neighbour order, core order, and (6) the split
-// between the small- and large-owner intersection launches.
+// prepare, plan, intersect, neighbour order, core order, then the begin and
+// end of the small-owner launches (6, 7) and of the large-owner launch (8,
+// 9), which may run concurrently on two streams.
 struct BuildProfileEvents {
-  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[10] = {};
   int32_t window_bits = 0;
   int32_t intersect_launches = 0;
   int32_t *plan_counts = nullptr;  // pinned int32[4], filled in stream order

@@ -664,10 +664,48 @@ static size_t big_lds_bytes(int wbits, int spc) {
   return ((size_t)1 << wbits) / 8 + (size_t)spc * (8 + 4 * 8) + 4 + sizeof(BigShared);
 }
 
+IntersectPlan::~IntersectPlan() {
+  if (ready) {
+    (void)hipEventSynchronize(ready);  // the copy into `host` is done
+    (void)hipEventDestroy(ready);
+  }
+  pinned_put(host);
+}
+
+scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int32_t *deg,
+                           DevArena &arena, hipStream_t s, IntersectPlan &p) {
+  static_assert(sizeof(PlanCounts) <= kPinnedBlock, "plan counts fit a pinned block");
+  p.n = n;
+  p.nnz = nnz;
+  if (nnz == 0) return SCAN_OK;
+  BigChunk *big_list;
+  PlanCounts *pc;
+  SCAN_TRY(arena.alloc(&p.small_list, n));
+  SCAN_TRY(arena.alloc(&p.heavy_list, n));
+  SCAN_TRY(arena.alloc(&big_list, nnz / cfg.spc + n + 1));
+  SCAN_TRY(arena.alloc(&pc, 1));
+  p.big_list = big_list;
+  p.counts = pc;
+  p.host = pinned_get();
+  if (!p.host) return fail(SCAN_ENOMEM, "pinned host allocation failed");
+  SCAN_HIP_TRY(hipEventCreateWithFlags(&p.ready, hipEventDisableTiming));
+  SCAN_HIP_TRY(hipMemsetAsync(pc, 0, sizeof(PlanCounts), s));
+  k_plan<<<grid_for(n, kPlanThreads * kPlanPer, 2048), kPlanThreads, 0, s>>>(deg, n, cfg.small_max, cfg.spc,
+                                                                             p.small_list, p.heavy_list, big_list, pc);
+  SCAN_HIP_TRY(hipMemcpyAsync(p.host, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
+  SCAN_HIP_TRY(hipEventRecord(p.ready, s));
+  return SCAN_OK;
+}
+
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
                           const int32_t *deg, const int32_t *adj, int kind, double *sims,
-                          int32_t *counts, int device, hipStream_t s, IntersectStats *stats) {
-  if (nnz == 0) return SCAN_OK;
+                          int32_t *counts, int device, hipStream_t s, IntersectStats *stats,
+                          hipStream_t side, const std::function<scan_status()> &after_launch,
+                          const IntersectPlan *plan) {
+  if (nnz == 0) {
+    if (side && side != s) SCAN_TRY(stream_wait(side, s));
+    return after_launch ? after_launch() : SCAN_OK;
+  }
   int lds_max = 65536, cus = 256;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -680,23 +718,20 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   if (big_lds_bytes(wbits, cfg.spc) > (size_t)lds_max) return fail(SCAN_EINVAL, "chunk size too large for LDS");
 
   DevArena tmp(s);
-  int32_t *small_list, *heavy_list;
-  BigChunk *big_list;
-  PlanCounts *pc;
-  const int64_t big_cap = nnz / cfg.spc + n + 1;
-  SCAN_TRY(tmp.alloc(&small_list, n));
-  SCAN_TRY(tmp.alloc(&heavy_list, n));
-  SCAN_TRY(tmp.alloc(&big_list, big_cap));
-  SCAN_TRY(tmp.alloc(&pc, 1));
-  SCAN_HIP_TRY(hipMemsetAsync(pc, 0, sizeof(PlanCounts), s));
-  k_plan<<<grid_for(n, kPlanThreads * kPlanPer, 2048), kPlanThreads, 0, s>>>(deg, n, cfg.small_max, cfg.spc, small_list,
-                                                 heavy_list, big_list, pc);
+  IntersectPlan own;
+  if (!plan) {
+    SCAN_TRY(intersect_plan(cfg, n, nnz, deg, tmp, s, own));
+    plan = &own;
+  }
+  if (plan->n != n || plan->nnz != nnz || !plan->ready) return fail(SCAN_EINVAL, "plan made for another graph");
+  const int32_t *small_list = plan->small_list, *heavy_list = plan->heavy_list;
+  const BigChunk *big_list = (const BigChunk *)plan->big_list;
+  PlanCounts *pc = (PlanCounts *)plan->counts;
   // The host reads the work counts to size the grids: one block per vertex
   // lets the hardware balance the uneven rows, which persistent grids with a
   // static split do not.
-  PlanCounts h;
-  SCAN_HIP_TRY(hipMemcpyAsync(&h, pc, sizeof(h), hipMemcpyDeviceToHost, s));
-  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  SCAN_HIP_TRY(hipEventSynchronize(plan->ready));
+  const PlanCounts h = *(const PlanCounts *)plan->host;
   if (stats) {
     stats->wbits = wbits;
     stats->launches = (h.small > 0) + (h.heavy > 0) + (h.big > 0);
@@ -705,28 +740,28 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
       stats->host_counts[1] = h.big;
       stats->host_counts[3] = h.heavy;
     }
-    if (stats->ev_start) (void)hipEventRecord(stats->ev_start, s);
   }
-  if (h.small || h.heavy) {
-    const size_t lds = small_lds_bytes(cfg.small_max);
-    if (lds > (size_t)lds_max) return fail(SCAN_EINVAL, "small_max too large for LDS");
-    if (lds > 65536) {
-      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<kSmallWaves>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<1>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
-    if (h.heavy)  // the longer rows first
-      k_small_owner<kSmallWaves><<<h.heavy, kSmallWaves * kWave, lds, s>>>(
-          heavy_list, &pc->heavy, nullptr, cfg.small_max, off, deg, adj, kind, sims, counts, cfg.skip_deg);
-    if (h.small) {
-      const int cap = std::min<int>(cfg.small_max, kLightDeg);  // light rows: LDS sized for them
-      k_small_owner<1><<<h.small, kWave, small_lds_bytes(cap), s>>>(small_list, &pc->small, nullptr, cap, off,
-                                                                    deg, adj, kind, sims, counts, cfg.skip_deg);
-    }
-    SCAN_HIP_TRY(hipGetLastError());
-  }
-  if (stats && stats->ev_mid) (void)hipEventRecord(stats->ev_mid, s);
+  auto mark = [&](hipEvent_t e, hipStream_t st) -> scan_status {
+    if (e) SCAN_HIP_TRY(hipEventRecord(e, st));
+    return SCAN_OK;
+  };
+  SCAN_TRY(mark(stats ? stats->ev_plan_end : nullptr, s));
+  if (side && side != s) SCAN_TRY(stream_wait(side, s));
+  // The large-owner kernel is persistent (one 1024-thread workgroup per CU,
+  // most of the LDS) and leaves wavefront slots, registers and some LDS free
+  // on every CU; the small-owner kernels, independent of it, run on the
+  // helper stream and fill them. The large one is launched first so that its
+  // workgroups are placed before the small ones take CUs.
+  // The two small-owner kernels take helper streams of their own, so that
+  // neither waits for the other.
+  auto fork = [&](int k, bool used) -> hipStream_t {
+    if (!used || !h.big) return s;
+    hipStream_t hs = helper_stream(k);
+    if (!hs || stream_wait(hs, s) != SCAN_OK) return s;
+    return hs;
+  };
+  const hipStream_t sh = fork(0, h.heavy > 0), sl = fork(1, h.small > 0);
+  JoinOnExit join_sh{s, sh}, join_sl{s, sl};  // before the plan lists are released
   if (h.big) {
     size_t lds = big_lds_bytes(wbits, cfg.spc);
     const bool one = n <= ((int64_t)1 << wbits);
@@ -748,6 +783,7 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
       SCAN_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (size_t)lds_max / lds));
     const int grid = (int)std::min<int64_t>((int64_t)cus * per_cu, h.big);
+    SCAN_TRY(mark(stats ? stats->ev_big_begin : nullptr, s));
     if (one)
       k_big_owner<true><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, nullptr,
                                                        nwin, kind, sims, counts, cfg.skip_deg);
@@ -755,8 +791,35 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
       k_big_owner<false><<<grid, kBigThreads, lds, s>>>(big_list, pc, cfg.spc, wbits, n, off, deg, adj, wt,
                                                         nwin, kind, sims, counts, cfg.skip_deg);
     SCAN_HIP_TRY(hipGetLastError());
+    SCAN_TRY(mark(stats ? stats->ev_big_end : nullptr, s));
+  } else {
+    SCAN_TRY(mark(stats ? stats->ev_big_begin : nullptr, s));
+    SCAN_TRY(mark(stats ? stats->ev_big_end : nullptr, s));
   }
-  if (stats && stats->ev_end) (void)hipEventRecord(stats->ev_end, s);
+  const hipStream_t ss = sh != s ? sh : sl;  // the small-owner events go on one of them
+  SCAN_TRY(mark(stats ? stats->ev_small_begin : nullptr, ss));
+  if (h.small || h.heavy) {
+    const size_t lds = small_lds_bytes(cfg.small_max);
+    if (lds > (size_t)lds_max) return fail(SCAN_EINVAL, "small_max too large for LDS");
+    if (lds > 65536) {
+      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<kSmallWaves>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    if (h.heavy)  // the longer rows first
+      k_small_owner<kSmallWaves><<<h.heavy, kSmallWaves * kWave, lds, sh>>>(
+          heavy_list, &pc->heavy, nullptr, cfg.small_max, off, deg, adj, kind, sims, counts, cfg.skip_deg);
+    if (h.small) {
+      const int cap = std::min<int>(cfg.small_max, kLightDeg);  // light rows: LDS sized for them
+      k_small_owner<1><<<h.small, kWave, small_lds_bytes(cap), sl>>>(small_list, &pc->small, nullptr, cap, off,
+                                                                     deg, adj, kind, sims, counts, cfg.skip_deg);
+    }
+    SCAN_HIP_TRY(hipGetLastError());
+  }
+  if (sl != ss) SCAN_TRY(stream_wait(ss, sl));  // the end event covers both
+  SCAN_TRY(mark(stats ? stats->ev_small_end : nullptr, ss));
+  if (after_launch) SCAN_TRY(after_launch());
   return SCAN_OK;
 }
 

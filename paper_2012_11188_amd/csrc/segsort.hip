@@ -696,47 +696,90 @@ __global__ __launch_bounds__(kSortBlock) void k_big_merge(
   }
 }
 
+SortClasses::~SortClasses() {
+  if (ready) {
+    (void)hipEventSynchronize(ready);  // the copy into `host` is done
+    (void)hipEventDestroy(ready);
+  }
+  pinned_put(host);
+}
+
+scan_status sort_classify(const int64_t *seg_off, int64_t nseg, DevArena &arena, hipStream_t s,
+                          SortClasses &c) {
+  static_assert(sizeof(SortStats) <= kPinnedBlock, "class sizes fit a pinned block");
+  c.nseg = nseg;
+  c.stream = s;
+  if (nseg <= 0) return SCAN_OK;
+  SortStats *st;
+  SCAN_TRY(arena.alloc(&c.lists, kNumCls * nseg));
+  SCAN_TRY(arena.alloc(&c.big_tiles_of, nseg));
+  SCAN_TRY(arena.alloc(&st, 1));
+  c.stats = st;
+  c.host = pinned_get();
+  if (!c.host) return fail(SCAN_ENOMEM, "pinned host allocation failed");
+  SCAN_HIP_TRY(hipEventCreateWithFlags(&c.ready, hipEventDisableTiming));
+  SCAN_HIP_TRY(hipMemsetAsync(st, 0, sizeof(SortStats), s));
+  k_classify<<<grid_for(nseg, kClassTile, 2048), 256, 0, s>>>(seg_off, nseg, c.lists, nseg, st, c.big_tiles_of);
+  SCAN_HIP_TRY(hipMemcpyAsync(c.host, st, sizeof(SortStats), hipMemcpyDeviceToHost, s));
+  SCAN_HIP_TRY(hipEventRecord(c.ready, s));
+  return SCAN_OK;
+}
+
 scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
                            const double *key_in, const int32_t *id_in, double *key_out,
                            int32_t *id_out, hipStream_t s) {
   if (nseg <= 0 || total <= 0) return SCAN_OK;
   DevArena arena(s);
-  int32_t *lists, *big_tiles_of;
-  SortStats *st;
-  SCAN_TRY(arena.alloc(&lists, kNumCls * nseg));
-  SCAN_TRY(arena.alloc(&big_tiles_of, nseg));
-  SCAN_TRY(arena.alloc(&st, 1));
-  SCAN_HIP_TRY(hipMemsetAsync(st, 0, sizeof(SortStats), s));
-  k_classify<<<grid_for(nseg, kClassTile, 2048), 256, 0, s>>>(seg_off, nseg, lists, nseg, st, big_tiles_of);
-  // The host reads the class sizes to size each grid (one block or wavefront
-  // per segment, which the hardware balances).
-  SortStats h;
-  SCAN_HIP_TRY(hipMemcpyAsync(&h, st, sizeof(SortStats), hipMemcpyDeviceToHost, s));
-  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  SortClasses c;
+  SCAN_TRY(sort_classify(seg_off, nseg, arena, s, c));
+  return sort_run(c, seg_off, total, key_in, id_in, key_out, id_out, s);
+}
+
+scan_status sort_run(const SortClasses &c, const int64_t *seg_off, int64_t total, const double *key_in,
+                     const int32_t *id_in, double *key_out, int32_t *id_out, hipStream_t s) {
+  const int64_t nseg = c.nseg;
+  if (nseg <= 0 || total <= 0) return SCAN_OK;
+  DevArena arena(s);
+  // The host waits for the class sizes (they size each grid: one block or
+  // wavefront per segment, which the hardware balances).
+  SCAN_HIP_TRY(hipEventSynchronize(c.ready));
+  const SortStats h = *(const SortStats *)c.host;
+  if (c.stream != s) SCAN_HIP_TRY(hipStreamWaitEvent(s, c.ready, 0));  // the class lists
+  SortStats *st = (SortStats *)c.stats;
+  const int32_t *lists = c.lists, *big_tiles_of = c.big_tiles_of;
   const int32_t *cnt = st->count;  // device copies of the class sizes
+  // The big segments' chain of launches (tile sorts, merge passes) runs on
+  // a helper stream, beside the other classes' kernels.
+  hipStream_t bs = s;
+  if (h.count[kClsBig] && h.count[kClsBig] < nseg) {
+    hipStream_t hs = helper_stream(0);
+    if (hs && stream_wait(hs, s) == SCAN_OK) bs = hs;
+  }
+  JoinOnExit join_bs{s, bs};
+  const hipStream_t gs = s, ms = s;
   if (h.count[kClsCopy])
-    k_sort_copy<<<grid_for(h.count[kClsCopy], 256), 256, 0, s>>>(seg_off, lists + kClsCopy * nseg, cnt + kClsCopy,
-                                                                 key_in, id_in, key_out, id_out);
+    k_sort_copy<<<grid_for(h.count[kClsCopy], 256), 256, 0, gs>>>(seg_off, lists + kClsCopy * nseg, cnt + kClsCopy,
+                                                                  key_in, id_in, key_out, id_out);
 #define SCAN_GROUP(S, C)                                                                      \
   if (h.count[C])                                                                              \
     k_sort_group<S><<<grid_for(((int64_t)h.count[C] + kWave / (S) - 1) / (kWave / (S)) * kWave, 256), 256, 0, \
-                      s>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, id_in, key_out, id_out);
+                      gs>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, id_in, key_out, id_out);
   SCAN_GROUP(8, kClsW8)
   SCAN_GROUP(16, kClsW16)
   SCAN_GROUP(32, kClsW32)
   SCAN_GROUP(64, kClsW64)
 #undef SCAN_GROUP
-#define SCAN_BLOCK(T, I, C)                                                                    \
+#define SCAN_BLOCK(T, I, C, ST)                                                                \
   static_assert((T) * (I) == class_cap(C), "block sort shape must match its class");          \
   if (h.count[C])                                                                              \
-    k_sort_block<T, I><<<grid_for(h.count[C], 1), T, 0, s>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, \
-                                                             id_in, key_out, id_out);
-  SCAN_BLOCK(64, 2, kClsB128)
-  SCAN_BLOCK(64, 4, kClsB256)
-  SCAN_BLOCK(64, 8, kClsB512)
-  SCAN_BLOCK(128, 8, kClsB1024)
-  SCAN_BLOCK(256, 8, kClsB2048)
-  SCAN_BLOCK(kSortBlock, kBigTile / kSortBlock, kClsB4096)
+    k_sort_block<T, I><<<grid_for(h.count[C], 1), T, 0, ST>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, \
+                                                              id_in, key_out, id_out);
+  SCAN_BLOCK(64, 2, kClsB128, ms)
+  SCAN_BLOCK(64, 4, kClsB256, ms)
+  SCAN_BLOCK(64, 8, kClsB512, ms)
+  SCAN_BLOCK(128, 8, kClsB1024, ms)
+  SCAN_BLOCK(256, 8, kClsB2048, s)
+  SCAN_BLOCK(kSortBlock, kBigTile / kSortBlock, kClsB4096, s)
 #undef SCAN_BLOCK
   if (h.count[kClsBig]) {
     const int32_t nbig = h.count[kClsBig];
@@ -752,16 +795,16 @@ scan_status segmented_sort(const int64_t *seg_off, int64_t nseg, int64_t total,
     SCAN_TRY(arena.alloc(&KB, total));
     SCAN_TRY(arena.alloc(&IA, total));
     SCAN_TRY(arena.alloc(&IB, total));
-    SCAN_TRY(exclusive_scan(big_tiles_of, tile_first, nbig, scan_ws, s));
+    SCAN_TRY(exclusive_scan(big_tiles_of, tile_first, nbig, scan_ws, bs));
     const int32_t *big_list = lists + kClsBig * nseg;
-    k_big_tiles<<<grid_for(nbig, 1, 4096), 256, 0, s>>>(big_tiles_of, tile_first, cnt + kClsBig, tile_seg);
-    k_big_tile_sort<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
+    k_big_tiles<<<grid_for(nbig, 1, 4096), 256, 0, bs>>>(big_tiles_of, tile_first, cnt + kClsBig, tile_seg);
+    k_big_tile_sort<<<grid_for(ntiles, 1), kSortBlock, 0, bs>>>(seg_off, big_list, tile_seg, tile_first,
                                                                &st->big_tiles, key_in, id_in, KA, IA);
     for (int q = 1; q <= h.max_passes; ++q) {
-      k_big_split<<<grid_for(ntiles * kWave, 256), 256, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
+      k_big_split<<<grid_for(ntiles * kWave, 256), 256, 0, bs>>>(seg_off, big_list, tile_seg, tile_first,
                                                                 &st->big_tiles, q, &st->max_passes, KA, IA, KB,
                                                                 IB, split);
-      k_big_merge<<<grid_for(ntiles, 1), kSortBlock, 0, s>>>(seg_off, big_list, tile_seg, tile_first,
+      k_big_merge<<<grid_for(ntiles, 1), kSortBlock, 0, bs>>>(seg_off, big_list, tile_seg, tile_first,
                                                              &st->big_tiles, q, &st->max_passes, split, KA, IA,
                                                              KB, IB, key_out, id_out);
     }

@@ -301,9 +301,12 @@ scan_status check_weights(const double *w, int64_t nnz, DevArena &tmp, hipStream
 
 scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, const int32_t *deg,
                                     const int32_t *adj, const double *w, double *sims, DevArena &tmp,
-                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_mid, hipEvent_t ev_end,
-                                    int32_t skip_deg) {
-  if (ev_start) SCAN_HIP_TRY(hipEventRecord(ev_start, s));
+                                    hipStream_t s, const IntersectStats *stats, int32_t skip_deg) {
+  auto mark = [&](hipEvent_t e) -> scan_status {
+    if (e) SCAN_HIP_TRY(hipEventRecord(e, s));
+    return SCAN_OK;
+  };
+  SCAN_TRY(mark(stats ? stats->ev_small_begin : nullptr));
   if (nnz > 0) {
     const int64_t units = (nnz + kWUnit - 1) / kWUnit;
     if (units > INT_MAX) return fail(SCAN_EINVAL, "graph too large for the weighted path");
@@ -314,13 +317,15 @@ scan_status weighted_similarity_all(int64_t n, int64_t nnz, const int64_t *off, 
     k_w_square_sums<<<grid_for(n * kWave, 256), 256, 0, s>>>(off, adj, w, n, S);
     k_w_unit_rows<<<grid_for(n, 256), 256, 0, s>>>(off, n, row_of);
     SCAN_HIP_TRY(hipGetLastError());
-    if (ev_mid) SCAN_HIP_TRY(hipEventRecord(ev_mid, s));
+    SCAN_TRY(mark(stats ? stats->ev_small_end : nullptr));
+    SCAN_TRY(mark(stats ? stats->ev_big_begin : nullptr));
     k_w_owner<<<(unsigned)units, kWThreads, 0, s>>>(off, deg, adj, w, S, row_of, n, nnz, sims, skip_deg);
     SCAN_HIP_TRY(hipGetLastError());
-  } else if (ev_mid) {
-    SCAN_HIP_TRY(hipEventRecord(ev_mid, s));
+  } else {
+    SCAN_TRY(mark(stats ? stats->ev_small_end : nullptr));
+    SCAN_TRY(mark(stats ? stats->ev_big_begin : nullptr));
   }
-  if (ev_end) SCAN_HIP_TRY(hipEventRecord(ev_end, s));
+  SCAN_TRY(mark(stats ? stats->ev_big_end : nullptr));
   return SCAN_OK;
 }
 
