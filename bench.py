@@ -97,6 +97,13 @@ def tune_str(t: dict) -> str:
     return f"small_max={t['small_max']} spc={t['spc']} wbits={t['wbits']}"
 
 
+def kernel_source_hash() -> str:
+    """sha256 of the intersection kernels' source: intersect.hip up to its
+    first host function."""
+    src = open(KERNEL_SRC, encoding="utf-8").read()
+    return hashlib.sha256(src[:src.index("IntersectPlan::~IntersectPlan")].encode()).hexdigest()
+
+
 def counter_traffic(tune: dict, workload: str):
     """Measured HBM bytes per k_big_owner launch from the committed rocprofv3
     counter summary, if it was taken on this kernel source, workload and
@@ -109,14 +116,14 @@ def counter_traffic(tune: dict, workload: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if kv.get("source_sha256") != src:
+    if kv.get("device_source_sha256") != kernel_source_hash():
         return None, "kernel source changed since the counters were taken"
     if kv.get("workload") != workload or kv.get("config") != tune_str(tune):
         return None, f"counters taken on {kv.get('workload')} / {kv.get('config')}"
-    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
-    write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"])
-    return fetch + write, "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration"
+    fetch = float(kv["fetch_bytes_per_dispatch"])
+    write = float(kv["write_bytes_per_dispatch"])
+    return fetch + write, ("rocprofv3: read requests by size (32/64/128 B x TCC_EA0_RDREQ_{32B,64B,128B}) + "
+                           "WRITE_SIZE; the size sum equals a 1 GiB copy and a 2 GiB reduction exactly")
 
 
 def timed_builds(scan, torch, build, steps: int, warmup: int):
@@ -187,12 +194,45 @@ def kernel_roofline(bm, phases, tune, workload):
             "traffic_over_algorithmic": (traffic / bm["k_big_owner"]) if traffic else None}
 
 
-def build_roofline(bm, total_ms):
+def library_source_hash() -> str:
+    """sha256 over every source file of the library (csrc/, sorted by name)."""
+    d = os.path.join(ROOT, "paper_2012_11188_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def build_counter_traffic(workload: str, tune: dict):
+    """Measured bytes between L2 and memory of one whole build (every kernel),
+    from profiles/build_<graph>_counters.txt, if taken on this library source
+    and shape; else None and the reason."""
+    path = os.path.join(ROOT, "profiles", f"build_{workload.split('_')[0]}_counters.txt")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("library_source_sha256") != library_source_hash():
+        return None, "library source changed since the counters were taken"
+    if kv.get("workload") != workload or kv.get("config") != tune_str(tune):
+        return None, f"counters taken on {kv.get('workload')} / {kv.get('config')}"
+    return float(kv["fetch_bytes_per_build"]) + float(kv["write_bytes_per_build"]), "rocprofv3, every kernel of one build"
+
+
+def build_roofline(bm, total_ms, workload=None, tune=None):
     sec = total_ms * 1e-3
+    traffic, why = build_counter_traffic(workload, tune) if workload and tune else (None, "not taken")
     return {"bytes": bm["build"], "achieved": bm["build"] / sec / 1e9, "frac": bm["build"] / sec / 1e9 / HBM_PEAK_GBS,
             "bytes_model": "s_off(n+1) + 56 nnz + 4 W_min (intersection probes are on-chip)",
             "model_bytes": bm["build_model"], "model_frac": bm["build_model"] / sec / 1e9 / HBM_PEAK_GBS,
-            "floor_bytes": bm["floor"], "floor_frac": bm["floor"] / sec / 1e9 / HBM_PEAK_GBS}
+            "floor_bytes": bm["floor"], "floor_frac": bm["floor"] / sec / 1e9 / HBM_PEAK_GBS,
+            "traffic": traffic, "traffic_source": why,
+            "traffic_frac": (traffic / sec / 1e9 / HBM_PEAK_GBS) if traffic else None}
 
 
 # ---------------------------------------------------------------------------
@@ -592,7 +632,7 @@ def rmat_workload(args, scan, torch, graphgen):
     extra = {"phases_ms": phases, "device_ms_per_step": dev_ms,
              "tune": dict(tinfo, **tune), "owner_split": split,
              "roofline": kernel_roofline(bm, phases, tune, workload),
-             "build_roofline": build_roofline(bm, phases["total_ms"]),
+             "build_roofline": build_roofline(bm, phases["total_ms"], workload, tune),
              "k_small_owner": {"bytes": bm["k_small_owner"], "model_bytes": bm["k_small_owner_model"],
                                "launch_ms": phases["intersect_small_ms"],
                                "achieved_gbs": bm["k_small_owner"] / max(phases["intersect_small_ms"], 1e-6) / 1e6}}

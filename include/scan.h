@@ -27,9 +27,11 @@
  *     ABI. Argument errors are detected before any device work is enqueued.
  *   - Streams: `stream` is a hipStream_t (NULL = the default stream). Device
  *     work is enqueued on it asynchronously unless a function says otherwise;
- *     the builds (scan_build_index*) are synchronous, see there.
+ *     the builds (scan_build_index*) wait on the host only for small
+ *     read-backs that size their grids, see there.
  *   - Ownership: the caller owns the CSR and every output buffer; the library
- *     never keeps a caller pointer after a call returns. The library owns each
+ *     keeps no caller pointer after a call returns, but device work a call has
+ *     enqueued may read the caller's device inputs until `stream` passes it. The library owns each
  *     scan_index and scan_server and their device memory until the matching
  *     free/destroy call.
  */
@@ -68,8 +70,11 @@ enum {
 
 /* Per-phase device times of a build made with SCAN_PROFILE, in milliseconds,
  * from hipEvents recorded on the build stream between phases:
- *   prepare     degrees, offsets, max degree (and validation if asked)
- *   plan        edge ownership and chunk lists per table class
+ *   prepare     degrees, offsets, max degree (and validation if asked),
+ *               the edge-ownership plan (chunk lists per table class) and
+ *               the read-back of both
+ *   plan        host tables of the later phases, up to the first
+ *               intersection launch (the device is idle here)
  *   intersect   all intersection + similarity launches, split into
  *               intersect_small (owners of degree <= small_max, one
  *               wavefront each) and intersect_big (bitmap-window owners)
@@ -93,8 +98,8 @@ typedef struct {
 
 /* A graph in CSR form. offsets has n+1 entries of offset_bits (32 or 64)
  * bits; adj has nnz int32 entries. on_device = 1: both are device pointers
- * (read during the build, not retained); 0: host pointers (copied to the
- * device first). */
+ * (read by the build's device work, not retained); 0: host pointers (copied
+ * to the device before the build call returns). */
 typedef struct {
   int64_t n;
   int64_t nnz;
@@ -146,15 +151,19 @@ scan_status scan_set_allocator(scan_alloc_fn alloc, scan_release_fn release, voi
 /* Builds the index of Section 3.2 (Algorithms 1 and 2) for graph g: degrees,
  * per-edge intersection + similarity, the neighbour-order segmented sort and
  * the core-order sort, run on `stream`.
- * Synchronous: the call returns once the build has completed on the device,
- * and *out is then ready for use on any stream. The host waits on `stream`
- * while the build runs, to read the maximum degree (it sizes the core-order
- * tables), the owner work counts (they size the intersection grids), the
- * size classes of each segmented sort (they size the sort grids) and, at the
- * end, for the device to finish with the host-side tables; with
- * SCAN_VALIDATE also for the validation result. Other work already queued on
- * `stream` is waited for too; builds on different streams therefore run one
- * after the other. The CSR may be freed once the call returns.
+ * Asynchronous: the call returns once every kernel of the build is enqueued;
+ * *out may be used on `stream` at once (that work is ordered after the
+ * build) and on another stream once it waits for `stream`. Inside the call
+ * the host waits only for small read-backs that size the grids: the maximum
+ * degree together with the owner work counts (one round trip after the
+ * degree pass, which also waits for work queued on `stream` before the
+ * build), and the size classes of each segmented sort (read back early into
+ * pinned memory, normally ready by the time they are needed); with
+ * SCAN_VALIDATE also for the validation result. Builds on different streams
+ * overlap on the device. A host-resident CSR may be freed once the call
+ * returns; a device-resident one is read until `stream` passes the build, so
+ * free it in stream order on `stream` (or with hipFree) and do not write it
+ * from another stream before then.
  * Errors: SCAN_EINVAL (null g/out/pointers with n > 0, n < 0, nnz < 0, odd
  * nnz, offset_bits not 32/64, unknown kind or flag, n or nnz too large for
  * int32 ids / the chosen offsets), SCAN_EGRAPH (SCAN_VALIDATE only),
@@ -182,8 +191,8 @@ scan_status scan_build_index_batch(const scan_csr *gs, int32_t count, scan_sim_k
  * fixed FP64 value per edge; with all weights 1 the index equals the
  * SCAN_SIM_COSINE one bit for bit. Neighbour order, core order and queries are
  * as for the other kinds; the index has no intersection counts. The weights
- * may be freed once the call returns (the build is synchronous, as
- * scan_build_index).
+ * follow the CSR's rules (host: may be freed once the call returns; device:
+ * read until `stream` passes the build).
  * Errors: as scan_build_index, plus SCAN_EINVAL for a null weights pointer
  * with nnz > 0 or SCAN_KEEP_COUNTS, and SCAN_EGRAPH (SCAN_VALIDATE only) for a
  * weight that is not finite. */
@@ -216,8 +225,9 @@ typedef struct {
 
 /* Builds the approximate index of graph g. kind: SCAN_SIM_COSINE or
  * SCAN_SIM_WEIGHTED_COSINE (SimHash, needs gauss) or SCAN_SIM_JACCARD
- * (MinHash, needs perm). Synchronous like scan_build_index: the inputs may be
- * freed once the call returns. Errors: as scan_build_index, plus SCAN_EINVAL for a
+ * (MinHash, needs perm). Inputs follow the CSR's rules of scan_build_index;
+ * this build also waits for the device after its LSH pass (it reads back
+ * the permutation check or keeps a host table until then). Errors: as scan_build_index, plus SCAN_EINVAL for a
  * null lsh, samples out of range, a missing draw array, weights with another
  * kind or none with SCAN_SIM_WEIGHTED_COSINE, SCAN_KEEP_COUNTS, or a
  * permutation value >= n. */

@@ -207,6 +207,27 @@ def _stream_handle(stream) -> int:
     return stream.cuda_stream
 
 
+def _hold_inputs(stream_handle: int, *objs) -> None:
+    """A build returns before the device has read its device inputs. When it
+    runs on a stream other than PyTorch's current one, the input tensors are
+    marked as used there, so that the caching allocator does not hand their
+    memory to the current stream while the build may still read it."""
+    import torch
+
+    if stream_handle == torch.cuda.current_stream().cuda_stream:
+        return
+    ext = None
+    todo = list(objs)
+    while todo:
+        o = todo.pop()
+        if isinstance(o, (tuple, list)):
+            todo.extend(o)
+        elif isinstance(o, torch.Tensor) and o.is_cuda and o.numel():
+            if ext is None:
+                ext = torch.cuda.ExternalStream(stream_handle)
+            o.record_stream(ext)
+
+
 def _ready():
     lib = load_library()
     _torch()
@@ -300,6 +321,7 @@ def scan_build_index(off, adj, kind: int = COSINE, flags: int = 0, stream=None, 
     s = _stream_handle(stream)
     out = ctypes.c_void_p()
     _check(lib.scan_build_index(ctypes.byref(c), int(kind), int(flags), ctypes.c_void_p(s), ctypes.byref(out)))
+    _hold_inputs(s, keep)
     del keep
     return Index(out.value, s)
 
@@ -330,6 +352,7 @@ def scan_build_index_weighted(off, adj, weights, flags: int = 0, stream=None) ->
     out = ctypes.c_void_p()
     _check(lib.scan_build_index_weighted(ctypes.byref(c), ctypes.c_void_p(ptr), int(flags), ctypes.c_void_p(s),
                                          ctypes.byref(out)))
+    _hold_inputs(s, keep, weights)
     del keep, weights
     return Index(out.value, s)
 
@@ -389,6 +412,7 @@ def scan_build_index_lsh(off, adj, kind: int, samples: int, gauss=None, perm=Non
     out = ctypes.c_void_p()
     _check(lib.scan_build_index_lsh(ctypes.byref(c), int(kind), ctypes.byref(spec), int(flags), ctypes.c_void_p(s),
                                     ctypes.byref(out)))
+    _hold_inputs(s, keep, kg, kp, kw)
     del keep, kg, kp, kw
     return Index(out.value, s)
 
@@ -414,6 +438,7 @@ def scan_build_index_batch(graphs, kind: int = COSINE, flags: int = 0, stream=No
     else:
         _check(lib.scan_build_index_ex(arr, len(arr), int(kind), int(flags), ctypes.byref(t), ctypes.c_void_p(s),
                                        outs))
+    _hold_inputs(s, keep)
     del keep
     return [Index(outs[i], s) for i in range(len(arr))]
 

@@ -71,30 +71,39 @@ void dev_free(void *p, size_t bytes, hipStream_t stream) {
 }
 
 static std::mutex g_pinned_mu;
-static std::vector<void *> g_pinned_free;
+static std::vector<PinnedBlock> g_pinned_free;
 
-void *pinned_get() {
+PinnedBlock pinned_take(size_t bytes) {
+  size_t cap = kPinnedBlock;
+  while (cap < bytes) cap <<= 1;
   {
     std::lock_guard<std::mutex> lk(g_pinned_mu);
-    if (!g_pinned_free.empty()) {
-      void *p = g_pinned_free.back();
-      g_pinned_free.pop_back();
-      return p;
-    }
+    for (size_t i = 0; i < g_pinned_free.size(); ++i)
+      if (g_pinned_free[i].cap == cap) {
+        const PinnedBlock b = g_pinned_free[i];
+        g_pinned_free[i] = g_pinned_free.back();
+        g_pinned_free.pop_back();
+        return b;
+      }
   }
-  void *p = nullptr;
-  if (hipHostMalloc(&p, kPinnedBlock, hipHostMallocDefault) != hipSuccess) {
+  PinnedBlock b;
+  if (hipHostMalloc(&b.p, cap, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
-    return nullptr;
+    return PinnedBlock{};
   }
-  return p;
+  b.cap = cap;
+  return b;
 }
 
-void pinned_put(void *p) {
-  if (!p) return;
+void pinned_give(const PinnedBlock &b) {
+  if (!b.p) return;
   std::lock_guard<std::mutex> lk(g_pinned_mu);
-  g_pinned_free.push_back(p);
+  g_pinned_free.push_back(b);
 }
+
+void *pinned_get() { return pinned_take(kPinnedBlock).p; }
+
+void pinned_put(void *p) { pinned_give(PinnedBlock{p, kPinnedBlock}); }
 
 static std::mutex g_helper_mu;
 static std::vector<hipStream_t> g_helper;  // kHelpers per device

@@ -25,6 +25,12 @@
 namespace scan {
 
 SharedArena::~SharedArena() {
+  if (!pinned.empty()) {  // staging copies may still be in flight
+    if (done) (void)hipEventSynchronize(done);
+    else (void)hipStreamSynchronize(stream);
+    for (auto &b : pinned) pinned_give(b);
+  }
+  if (done) (void)hipEventDestroy(done);
   for (auto &a : allocs) dev_free(a.p, a.bytes, stream);
 }
 
@@ -449,12 +455,23 @@ scan_status arena_alloc(SharedArena &a, T **p, int64_t count) {
   return SCAN_OK;
 }
 
-template <class T>
-scan_status to_device(DevArena &tmp, T **dst, const std::vector<T> &src, hipStream_t s) {
-  SCAN_TRY(tmp.alloc(dst, (int64_t)src.size()));
-  if (!src.empty())
-    SCAN_HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+// Copies bytes from host memory to dst through a pinned block that the arena
+// holds until the build's end has passed, so the call does not wait for the
+// copy and src may go at once.
+scan_status upload_pinned(SharedArena &a, void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (!bytes) return SCAN_OK;
+  const PinnedBlock b = pinned_take(bytes);
+  if (!b.p) return fail(SCAN_ENOMEM, "pinned host allocation of %zu bytes failed", bytes);
+  a.pinned.push_back(b);
+  std::memcpy(b.p, src, bytes);
+  SCAN_HIP_TRY(hipMemcpyAsync(dst, b.p, bytes, hipMemcpyHostToDevice, s));
   return SCAN_OK;
+}
+
+template <class T>
+scan_status to_device(SharedArena &a, DevArena &tmp, T **dst, const std::vector<T> &src, hipStream_t s) {
+  SCAN_TRY(tmp.alloc(dst, (int64_t)src.size()));
+  return upload_pinned(a, *dst, src.data(), src.size() * sizeof(T), s);
 }
 
 // Host tables gathered into one buffer (each entry 16-byte aligned) and sent
@@ -468,11 +485,9 @@ class HostPack {
     if (!v.empty()) std::memcpy(buf_.data() + at, v.data(), v.size() * sizeof(T));
     return at;
   }
-  scan_status upload(DevArena &tmp, hipStream_t s, unsigned char **dev) {
+  scan_status upload(SharedArena &a, DevArena &tmp, hipStream_t s, unsigned char **dev) {
     SCAN_TRY(tmp.alloc(dev, (int64_t)std::max<size_t>(buf_.size(), 16)));
-    if (!buf_.empty())
-      SCAN_HIP_TRY(hipMemcpyAsync(*dev, buf_.data(), buf_.size(), hipMemcpyHostToDevice, s));
-    return SCAN_OK;
+    return upload_pinned(a, *dev, buf_.data(), buf_.size(), s);
   }
   template <class T>
   static const T *at(const unsigned char *dev, size_t off) {
@@ -578,19 +593,14 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     for (int64_t i0 = 0; i0 < items; i0 += kPrepTile)
       ptiles.push_back(PrepTile{g, 0, i0, std::min(items, i0 + kPrepTile)});
   }
-  SCAN_TRY(to_device(tmp, &d_gd, hd, s));
-  SCAN_TRY(to_device(tmp, &d_ptiles, ptiles, s));
-  SCAN_HIP_TRY(hipMemsetAsync(d_dmax, 0, (size_t)G * 4, s));
-  SCAN_HIP_TRY(hipMemsetAsync(off_u, 0, 8, s));
   {
-    const int64_t total = item_base[G];
     // graphs without vertices contribute only their (zero) end offset
     std::vector<GraphDesc> fix = hd;
     bool any_empty = false;
     for (int32_t g = 0; g < G; ++g)
       if (gs[g].n == 0) any_empty = true;
-    int64_t *zero_off = nullptr;
     if (any_empty) {
+      int64_t *zero_off;
       SCAN_TRY(tmp.alloc(&zero_off, 1));
       SCAN_HIP_TRY(hipMemsetAsync(zero_off, 0, 8, s));
       for (int32_t g = 0; g < G; ++g)
@@ -598,9 +608,14 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
           fix[g].off = zero_off;
           fix[g].off_bits = 64;
         }
-      SCAN_HIP_TRY(hipMemcpyAsync(d_gd, fix.data(), fix.size() * sizeof(GraphDesc), hipMemcpyHostToDevice, s));
-      SCAN_HIP_TRY(hipStreamSynchronize(s));
     }
+    SCAN_TRY(to_device(*arena, tmp, &d_gd, fix, s));
+  }
+  SCAN_TRY(to_device(*arena, tmp, &d_ptiles, ptiles, s));
+  SCAN_HIP_TRY(hipMemsetAsync(d_dmax, 0, (size_t)G * 4, s));
+  SCAN_HIP_TRY(hipMemsetAsync(off_u, 0, 8, s));
+  {
+    const int64_t total = item_base[G];
     if (total > 0)
       k_union_prepare<<<grid_for((int64_t)ptiles.size(), 1, 4096), kPrepThreads, 0, s>>>(
           d_gd, d_ptiles, (int64_t)ptiles.size(), copy_adj ? 1 : 0, off_u, deg, adj_u, d_dmax);
@@ -695,9 +710,18 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   }
   if (!sims) SCAN_TRY(tmp.alloc(&sims, NNZ));
 
+  // The one wait of the build that stalls the device: the maximum degrees
+  // (with the plan counts) size everything after.
   std::vector<unsigned> hdmax(G);
-  SCAN_HIP_TRY(hipMemcpyAsync(hdmax.data(), d_dmax, (size_t)G * 4, hipMemcpyDeviceToHost, s));
-  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  {
+    const PinnedBlock hb = pinned_take((size_t)G * 4);
+    if (!hb.p) return fail(SCAN_ENOMEM, "pinned host allocation failed");
+    hipError_t e = hipMemcpyAsync(hb.p, d_dmax, (size_t)G * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) std::memcpy(hdmax.data(), hb.p, (size_t)G * 4);
+    pinned_give(hb);
+    SCAN_HIP_TRY(e);
+  }
   SCAN_HIP_TRY(hipGetLastError());
   mark(1);
 
@@ -726,7 +750,7 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
                p_segbase = pack.add(segbase), p_ng = pack.add(ng), p_obase = pack.add(obase),
                p_vbase = pack.add(vbase), p_ebase = pack.add(ebase), p_vt = pack.add(vt), p_rt = pack.add(rt);
   unsigned char *dpack;
-  SCAN_TRY(pack.upload(tmp, s, &dpack));
+  SCAN_TRY(pack.upload(*arena, tmp, s, &dpack));
   const int64_t *d_hbase = pack.at<int64_t>(dpack, p_hbase), *d_Ebase = pack.at<int64_t>(dpack, p_Ebase),
                 *d_cobase = pack.at<int64_t>(dpack, p_cobase), *d_segbase = pack.at<int64_t>(dpack, p_segbase),
                 *d_ng = pack.at<int64_t>(dpack, p_ng), *d_obase = pack.at<int64_t>(dpack, p_obase),
@@ -850,9 +874,11 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
                                                             off_local);
   }
   SCAN_HIP_TRY(hipGetLastError());
-  // The temporaries are released in stream order; the host tables above must
-  // outlive their copy, which this wait guarantees.
-  SCAN_HIP_TRY(hipStreamSynchronize(s));
+  // The build returns without waiting for the device: the temporaries are
+  // released in stream order, and the pinned staging of the host tables
+  // goes back to the pool once this event has passed.
+  SCAN_HIP_TRY(hipEventCreateWithFlags(&arena->done, hipEventDisableTiming));
+  SCAN_HIP_TRY(hipEventRecord(arena->done, s));
 
   for (int32_t g = 0; g < G; ++g) {
     scan_index *ix = new scan_index();

@@ -158,10 +158,19 @@ scan_status exclusive_scan(const int32_t *in, int64_t *out, int64_t n, int64_t *
 scan_status exclusive_scan64(const int64_t *in, int64_t *out, int64_t n, int64_t *ws,
                              hipStream_t s);
 
-// Small blocks of pinned host memory (kPinnedBlock bytes each) for values
-// the host reads back from the device while other work runs; reused across
-// calls. Null if pinned memory cannot be had.
+// Pinned host memory, pooled across calls: staging for host tables sent to
+// the device and for values read back while other work runs. A block holds
+// at least the bytes asked for (a power of two, at least kPinnedBlock); p is
+// null if pinned memory cannot be had. A block goes back to the pool only
+// once every copy that uses it has completed.
 constexpr size_t kPinnedBlock = 4096;
+struct PinnedBlock {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+PinnedBlock pinned_take(size_t bytes);
+void pinned_give(const PinnedBlock &b);
+// One kPinnedBlock block (null on failure) and its return.
 void *pinned_get();
 void pinned_put(void *p);
 

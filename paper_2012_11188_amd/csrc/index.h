@@ -124,6 +124,10 @@ struct SharedArena {
   hipStream_t stream = nullptr;
   std::vector<DevAlloc> allocs;
   int64_t bytes = 0;
+  // Pinned staging of the build's host tables, returned to the pool once
+  // `done` (recorded at the end of the build) has completed.
+  std::vector<PinnedBlock> pinned;
+  hipEvent_t done = nullptr;
   ~SharedArena();
 };
 
