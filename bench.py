@@ -645,10 +645,13 @@ def rmat_workload(args, scan, torch, graphgen):
         log(f"lsh: {extra['lsh']}")
         if not args.no_quality:
             qual = [approx_quality(scan, torch, graphgen, "rmat20", g, off, adj, 256)]
-            s2 = graphgen.sbm2000()
+            # planted communities dense enough that every vertex is above
+            # both degree thresholds at k = 64 (all edges approximated):
+            # 20 blocks of 200, p_in = 0.6, p_out = 0.01 (degree about 157)
+            s2 = graphgen.sbm(4000, 20, 0.6, 0.01, seed=4000)
             o2 = torch.from_numpy(s2.off.astype(np.int32)).cuda()
             a2 = torch.from_numpy(s2.adj).cuda()
-            qual.append(approx_quality(scan, torch, graphgen, "sbm2000", s2, o2, a2, 64))
+            qual.append(approx_quality(scan, torch, graphgen, "sbm4000_dense", s2, o2, a2, 64))
             extra["approx_quality"] = qual
             log(f"approximate quality: {qual}")
     if scale == 20 and not args.no_weighted:
