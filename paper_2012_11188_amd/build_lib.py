@@ -19,9 +19,17 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
+# The atomic optimizer folds a wavefront's uniform atomics into one (DPP).
+# intersect.hip issues its few wavefront-level LDS atomics from one lane by
+# hand and reads their results later, which the optimizer would defeat (it
+# broadcasts each result, and so waits for it, right after the atomic).
+ATOMIC_STRATEGY = {"intersect.hip": "None"}
+
+
+def flags_for(src: str) -> list:
+    return [*FLAGS, "-mllvm", f"-amdgpu-atomic-optimizer-strategy={ATOMIC_STRATEGY.get(src, 'DPP')}"]
 
 
 def build(verbose: bool = False) -> str:
@@ -30,7 +38,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *flags_for(src), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

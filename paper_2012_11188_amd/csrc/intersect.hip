@@ -255,7 +255,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
       int32_t base = 0;
       if (m) {
         const int leader = __ffsll((unsigned long long)m) - 1;
-        base = __builtin_amdgcn_readlane(atomicAdd(&s_nlow, lane == leader ? __popcll(m) : 0), leader);
+        int32_t old = 0;
+        if (lane == leader) old = atomicAdd(&s_nlow, __popcll(m));
+        base = __builtin_amdgcn_readlane(old, leader);
       }
       if (low) {
         const int32_t j = base + __popcll(m & lanes_below());
@@ -429,7 +431,9 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       int32_t base = 0;
       if (mk) {
         const int leader = __ffsll((unsigned long long)mk) - 1;
-        base = __builtin_amdgcn_readlane(atomicAdd(&sh->nlow, lane == leader ? __popcll(mk) : 0), leader);
+        int32_t old = 0;
+        if (lane == leader) old = atomicAdd(&sh->nlow, __popcll(mk));
+        base = __builtin_amdgcn_readlane(old, leader);
       }
       if (low) {
         const int k = base + __popcll(mk & lanes_below());
@@ -471,7 +475,9 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         if (tid == 0) sh->next = 0;
         __syncthreads();
         for (;;) {
-          const int32_t i = uniform(atomicAdd(&sh->next, lane == 0 ? 1 : 0));
+          int32_t old = 0;
+          if (lane == 0) old = atomicAdd(&sh->next, 1);
+          const int32_t i = __builtin_amdgcn_readlane(old, 0);
           if (i >= nlow) break;
           const int32_t du = uniform(le_du[i]);
           const int32_t *row = adj + uniform64(le_ou[i]);
@@ -493,11 +499,17 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       if (tid == 0) sh->next = 0;
       __syncthreads();
       const int32_t nitems = nlow + uniform(sh->nextra);
-      // Work items are claimed from the LDS counter. Every lane adds 1 (a uniform operand, which the compiler folds into
-      // one atomic of the active-lane count), so a claim advances the
-      // counter by kWave and the item index is the old value / kWave.
-      auto claim = [&](int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou) {
-        const int32_t j = uniform(atomicAdd(&sh->next, 1)) / kWave;
+      // Work items are claimed from the LDS counter, one lane adding 1.
+      // A claim is split in two: take() issues the LDS atomic, resolve()
+      // turns its result into an item. Between the two the wavefront probes
+      // its current item, so the atomic's round trip is not on its path.
+      auto take = [&]() -> int32_t {
+        int32_t old = 0;
+        if (lane == 0) old = atomicAdd(&sh->next, 1);
+        return old;
+      };
+      auto resolve = [&](int32_t tok, int32_t &e, int32_t &lo, int32_t &hi, int64_t &ou) {
+        const int32_t j = __builtin_amdgcn_readlane(tok, 0);
         if (j >= nitems) {
           e = -1;
           lo = hi = 0;
@@ -580,22 +592,25 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
           if (kOneWindow) atomicAdd(&le_lt[e], (int32_t)(t >> 16));
         }
       };
-      // Items are claimed one step further ahead, after a probe has freed
-      // its registers, so no claim waits on loads in flight.
+      // Items are claimed one step further ahead: the claim's atomic goes
+      // out before a probe and is resolved after it, when the probe has
+      // freed its registers, so no claim waits on loads in flight.
       int32_t ea, loa, hia, eb, lob, hib;
       int64_t oua, oub;
       int32_t xa[kItemLoads], xb[kItemLoads];
-      claim(ea, loa, hia, oua);
+      resolve(take(), ea, loa, hia, oua);
       fetch_item(xa, oua, loa, hia - loa);
-      claim(eb, lob, hib, oub);
+      resolve(take(), eb, lob, hib, oub);
       while (ea >= 0) {
         fetch_item(xb, oub, lob, hib - lob);
+        const int32_t ta = take();
         probe_item(xa, ea, hia - loa);
-        claim(ea, loa, hia, oua);
+        resolve(ta, ea, loa, hia, oua);
         if (eb < 0) break;
         fetch_item(xa, oua, loa, hia - loa);
+        const int32_t tb = take();
         probe_item(xb, eb, hib - lob);
-        claim(eb, lob, hib, oub);
+        resolve(tb, eb, lob, hib, oub);
       }
       __syncthreads();
       for (int64_t i = p + tid; i < pe; i += blockDim.x) {
