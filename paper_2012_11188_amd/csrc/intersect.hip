@@ -323,6 +323,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
 // Big owners: persistent workgroups with an LDS bitmap window.
 
 constexpr int kBigThreads = 1024;
+#ifndef SCAN_BIG_RUN
+#define SCAN_BIG_RUN 4
+#endif
 constexpr int kUnroll = 4;   // ids per lane per probe group
 constexpr int kSeg = 1024;   // most ids per work item (rows longer than this are split)
 
@@ -337,6 +340,7 @@ __device__ __forceinline__ uint32_t bitmap_word(uint32_t y) {
 
 struct BigShared {
   int32_t chunk;
+  int32_t run_next, run_left;  // the rest of the workgroup's current run of chunks
   int32_t nlow;
   int32_t next;
   int32_t nextra;
@@ -402,10 +406,23 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
 
   const int32_t nchunks = pc->big;  // written by k_plan: no host round trip
   for (int i = tid; i < nwords; i += blockDim.x) bm[i] = 0u;
+  if (tid == 0) sh->run_left = 0;
+  // With one window, chunks are claimed in runs of kRun consecutive ones:
+  // a high-degree owner's chunks are consecutive, so a run often keeps one
+  // owner, and the owner's bits stay in the bitmap from chunk to chunk
+  // (they are cleared only when the next chunk has another owner).
+  constexpr int32_t kRun = kOneWindow ? SCAN_BIG_RUN : 1;
+  int32_t held = -1, held_dh = 0;  // the owner whose bits the bitmap holds
+  int64_t held_oh = 0;
   for (;;) {
     __syncthreads();
     if (tid == 0) {
-      sh->chunk = atomicAdd(&pc->counter, 1);
+      if (sh->run_left == 0) {
+        sh->run_next = atomicAdd(&pc->counter, kRun);
+        sh->run_left = kRun;
+      }
+      sh->chunk = sh->run_next++;
+      --sh->run_left;
       sh->nlow = 0;
     }
     __syncthreads();
@@ -450,6 +467,19 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
     __syncthreads();
     const int nlow = uniform(sh->nlow);
     if (nlow == 0) continue;
+    if (one_window && h != held) {
+      if (held >= 0) {
+        for (int i = tid; i < held_dh; i += blockDim.x) bm[(uint32_t)adj[held_oh + i] >> 5] = 0u;
+        __syncthreads();  // the new owner's bits may share words with the old one's
+      }
+      for (int i = tid; i < dh; i += blockDim.x) {
+        const int32_t x = adj[oh + i];
+        atomicOr(&bm[x >> 5], 1u << (x & 31));
+      }
+      held = h;
+      held_oh = oh;
+      held_dh = dh;
+    }
     // Windows of ids [w0, w0 + W) that hold ids of N(h), in increasing order.
     int64_t p = 0;
     while (p < dh) {
@@ -457,7 +487,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       const int64_t pe = one_window ? dh
                          : wt ? (int64_t)wt[(int64_t)h * (nwin + 1) + (w0 >> wbits) + 1]
                               : wave_lower_bound(adj + oh, p, dh, (int32_t)min(w0 + W, (int64_t)INT32_MAX));
-      for (int64_t i = p + tid; i < pe; i += blockDim.x) {
+      for (int64_t i = p + tid; !one_window && i < pe; i += blockDim.x) {
         const int32_t x = (int32_t)(adj[oh + i] - w0);
         atomicOr(&bm[x >> 5], 1u << (x & 31));
       }
@@ -613,7 +643,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         resolve(tb, eb, lob, hib, oub);
       }
       __syncthreads();
-      for (int64_t i = p + tid; i < pe; i += blockDim.x) {
+      for (int64_t i = p + tid; !one_window && i < pe; i += blockDim.x) {
         const int32_t x = (int32_t)(adj[oh + i] - w0);
         bm[x >> 5] = 0u;
       }
