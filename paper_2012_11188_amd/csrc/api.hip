@@ -358,7 +358,7 @@ scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind,
     return SCAN_OK;
   };
   SCAN_TRY(sweep(&IntersectConfig::small_max, {32, 64, 128, 256, 512, 1024}));
-  SCAN_TRY(sweep(&IntersectConfig::spc, {128, 256, 512, 1024}));
+  SCAN_TRY(sweep(&IntersectConfig::spc, {128, 256, 512, 768, 1024}));
   SCAN_TRY(sweep(&IntersectConfig::wbits, {17, 18, 19, 20}));
   *best = scan_tune{cur.small_max, cur.spc, cur.wbits, 0};
   if (best_ms) *best_ms = cur_ms;

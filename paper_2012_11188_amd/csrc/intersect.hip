@@ -481,7 +481,12 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       held_dh = dh;
     }
     // Windows of ids [w0, w0 + W) that hold ids of N(h), in increasing order.
+    // With the window table, thread i < nlow reads edge i's range in the
+    // next window while the current window's items run (pf_w: the window
+    // its prefetched pair belongs to).
     int64_t p = 0;
+    int32_t pf0 = 0, pf1 = 0;
+    int64_t pf_w = -1;
     while (p < dh) {
       const int64_t w0 = one_window ? 0 : ((int64_t)adj[oh + p] >> wbits) << wbits;
       const int64_t pe = one_window ? dh
@@ -492,14 +497,19 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
         atomicOr(&bm[x >> 5], 1u << (x & 31));
       }
       if (!one_window && wt) {
-        // each lower neighbour's ids inside this window, from the table
+        // each lower neighbour's ids inside this window, from the table;
+        // thread i reads back only its own edge's range before the scan's
+        // barriers, so no barrier is needed here (nlow <= spc <= blockDim)
         const int64_t kw = w0 >> wbits;
-        for (int i = tid; i < nlow; i += blockDim.x) {
-          const int32_t *t = wt + (int64_t)le_u[i] * (nwin + 1) + kw;
-          le_b0[i] = t[0];
-          le_b1[i] = t[1];
+        if (tid < nlow) {
+          if (pf_w != kw) {
+            const int32_t *t = wt + (int64_t)le_u[tid] * (nwin + 1) + kw;
+            pf0 = t[0];
+            pf1 = t[1];
+          }
+          le_b0[tid] = pf0;
+          le_b1[tid] = pf1;
         }
-        __syncthreads();
       } else if (!one_window) {
         // each lower neighbour's ids inside this window, after the last one
         if (tid == 0) sh->next = 0;
@@ -529,6 +539,13 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
       if (tid == 0) sh->next = 0;
       __syncthreads();
       const int32_t nitems = nlow + uniform(sh->nextra);
+      if (!one_window && wt && pe < dh && tid < nlow) {  // the next window's ranges, read during the items
+        const int64_t kwn = (int64_t)adj[oh + pe] >> wbits;
+        const int32_t *t = wt + (int64_t)le_u[tid] * (nwin + 1) + kwn;
+        pf0 = t[0];
+        pf1 = t[1];
+        pf_w = kwn;
+      }
       // Work items are claimed from the LDS counter, one lane adding 1.
       // A claim is split in two: take() issues the LDS atomic, resolve()
       // turns its result into an item. Between the two the wavefront probes
