@@ -76,6 +76,19 @@ __device__ __forceinline__ int32_t uf_find(int32_t *parent, int32_t x) {
   return cur;
 }
 
+// The root of x without writing: k_q_jump needs every core's final pointer to
+// be its root, and a halving step of another thread, based on pointers read
+// before this thread stored the root, could overwrite it with an ancestor.
+__device__ __forceinline__ int32_t uf_root(const int32_t *parent, int32_t x) {
+  int32_t cur = x;
+  for (int guard = 0; guard < (1 << 26); ++guard) {
+    const int32_t nxt = __atomic_load_n(&parent[cur], __ATOMIC_RELAXED);
+    if (nxt == cur) return cur;
+    cur = nxt;
+  }
+  return cur;
+}
+
 __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) {
   for (;;) {
     a = uf_find(parent, a);
@@ -149,7 +162,7 @@ __global__ void k_q_jump(IndexView ix, const QueryDesc *qd) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q.K;
        i += (int64_t)gridDim.x * blockDim.x) {
     int32_t u = ix.co_ids[q.base + i];
-    q.parent[u] = uf_find(q.parent, u);
+    __atomic_store_n(&q.parent[u], uf_root(q.parent, u), __ATOMIC_RELAXED);
   }
 }
 

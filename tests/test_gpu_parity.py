@@ -258,3 +258,23 @@ def test_queries_on_two_streams():
     torch.cuda.synchronize()
     for mu, eps, m in outs:
         assert np.array_equal(m.cpu().numpy(), oracle.query(oix, mu, eps)[0])
+
+
+def test_query_labels_repeatable():
+    """Every core's label is its component's root after pointer jumping, on
+    every run: the same queries, repeated, all equal the oracle. (A
+    compressing find in the jumping step could overwrite a stored root with
+    an ancestor read before it.)"""
+    import torch
+
+    g = graphgen.rmat(14, 16, seed=14)
+    say("rmat", 14, g.nnz, "repeat")
+    gix = gpu_build(g, scan.JACCARD, bits=64)
+    oix = oracle.build_index(g, scan.JACCARD, threads=8)
+    pairs = query_grid(oix.dmax, oix.sim)[:24]
+    want = {p: oracle.query(oix, *p)[0] for p in pairs}
+    for rep in range(6):
+        for mu, eps in pairs:
+            memb, _ = scan.scan_query_ex(gix, mu, eps)
+            torch.cuda.synchronize()
+            assert np.array_equal(memb.cpu().numpy(), want[(mu, eps)]), (rep, mu, eps)
