@@ -654,6 +654,17 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   // the maximum degrees below.
   IntersectPlan plan;
   if (NNZ > 0 && !weighted) SCAN_TRY(intersect_plan(cfg, N, NNZ, deg, tmp, s, plan));
+  // The small-owner kernels' helper streams wait for the plan now, off the
+  // path between the read-back and the first intersection launch.
+  JoinOnExit join_h0{s, nullptr}, join_h1{s, nullptr};
+  if (NNZ > 0 && !weighted) {
+    for (int k = 0; k < 2; ++k) {
+      hipStream_t hs = helper_stream(k);
+      if (hs && stream_wait(hs, s) == SCAN_OK) plan.helper[k] = hs;
+    }
+    join_h0.helper = plan.helper[0];
+    join_h1.helper = plan.helper[1];
+  }
   const double *w_dev = weights;  // edge weights on the device (weighted cosine)
   if (weighted && NNZ > 0) {
     if (!gs[0].on_device) {
@@ -710,6 +721,15 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   }
   if (!sims) SCAN_TRY(tmp.alloc(&sims, NNZ));
 
+  // Tiles of the core-order kernels (they need no maximum degree): built
+  // here, while the device runs the degree pass and the plan.
+  std::vector<VTile> vt;
+  std::vector<RTile> rt;
+  for (int32_t g = 0; g < G; ++g) {
+    for (int64_t v0 = vbase[g]; v0 < vbase[g + 1]; v0 += kRankTile)
+      vt.push_back(VTile{g, 0, v0, std::min(vbase[g + 1], v0 + kRankTile)});
+    for (int64_t r0 = 0; r0 < gs[g].n; r0 += kFillRanks) rt.push_back(RTile{g, (int32_t)r0});
+  }
   // The one wait of the build that stalls the device: the maximum degrees
   // (with the plan counts) size everything after.
   std::vector<unsigned> hdmax(G);
@@ -737,13 +757,6 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     segbase[g + 1] = segbase[g] + hdmax[g];  // segments mu = 2..dmax+1
     obase[g + 1] = obase[g] + gs[g].n + 1;
     ng[g] = gs[g].n;
-  }
-  std::vector<VTile> vt;
-  std::vector<RTile> rt;
-  for (int32_t g = 0; g < G; ++g) {
-    for (int64_t v0 = vbase[g]; v0 < vbase[g + 1]; v0 += kRankTile)
-      vt.push_back(VTile{g, 0, v0, std::min(vbase[g + 1], v0 + kRankTile)});
-    for (int64_t r0 = 0; r0 < gs[g].n; r0 += kFillRanks) rt.push_back(RTile{g, (int32_t)r0});
   }
   HostPack pack;
   const size_t p_hbase = pack.add(hbase), p_Ebase = pack.add(Ebase), p_cobase = pack.add(cobase),

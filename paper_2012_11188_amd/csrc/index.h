@@ -44,6 +44,9 @@ struct IntersectPlan {
   void *big_list = nullptr, *counts = nullptr;  // device chunk list and counts
   void *host = nullptr;                         // pinned copy of the counts
   hipEvent_t ready = nullptr;
+  // helper streams already ordered after the plan (set by the caller), used
+  // for the two small-owner kernels; null: intersect_all orders its own
+  hipStream_t helper[2] = {nullptr, nullptr};
   IntersectPlan() = default;
   IntersectPlan(const IntersectPlan &) = delete;
   IntersectPlan &operator=(const IntersectPlan &) = delete;

@@ -818,6 +818,7 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   // neither waits for the other.
   auto fork = [&](int k, bool used) -> hipStream_t {
     if (!used || !h.big) return s;
+    if (plan->helper[k]) return plan->helper[k];  // ordered after the plan by the caller
     hipStream_t hs = helper_stream(k);
     if (!hs || stream_wait(hs, s) != SCAN_OK) return s;
     return hs;
