@@ -219,14 +219,22 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
             const int cnt = __popcll(__ballot(valid));      // the valid lanes are a prefix
             const uint64_t hm = __ballot(selfh);
             if (hm) mp = c + __ffsll((unsigned long long)hm) - 1;
-            for (uint64_t cm = __ballot(hit || selfh); cm; cm &= cm - 1) {
-              const int k = __ffsll((unsigned long long)cm) - 1;
-              const int32_t xk = __builtin_amdgcn_readlane(x, k);
-              if (!ldone && l < xk) {  // x = l comes before xk
-                acc += whl;
-                ldone = true;
+            // The products of the common ids, in lane (= ascending id)
+            // order; the x = l term goes before the first of them above l.
+            uint64_t cm = __ballot(hit || selfh);
+            uint64_t after = 0;
+            if (!ldone) {
+              const uint64_t above = __ballot((hit || selfh) && x > l);
+              if (above) {
+                after = cm & ~((1ull << (__ffsll((unsigned long long)above) - 1)) - 1ull);
+                cm &= ~after;
               }
-              acc += lane_f64(prod, k);
+            }
+            for (; cm; cm &= cm - 1) acc += lane_f64(prod, __ffsll((unsigned long long)cm) - 1);
+            if (after) {
+              acc += whl;
+              ldone = true;
+              for (cm = after; cm; cm &= cm - 1) acc += lane_f64(prod, __ffsll((unsigned long long)cm) - 1);
             }
             if (cnt < kWave && c + cnt < du) nx = __builtin_amdgcn_readlane(x, cnt);
             return cnt;
