@@ -40,7 +40,6 @@ BuildProfileEvents::~BuildProfileEvents() {
       (void)hipEventSynchronize(e);
       (void)hipEventDestroy(e);
     }
-  if (plan_counts) (void)hipHostFree(plan_counts);
 }
 
 // Per-graph description of a batch member (device copy).
@@ -547,8 +546,6 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   if (flags & SCAN_PROFILE) {
     prof = std::make_shared<BuildProfileEvents>();
     for (auto &e : prof->ev) SCAN_HIP_TRY(hipEventCreate(&e));
-    SCAN_HIP_TRY(hipHostMalloc((void **)&prof->plan_counts, 4 * sizeof(int32_t), hipHostMallocDefault));
-    for (int k = 0; k < 4; ++k) prof->plan_counts[k] = 0;
   }
   auto mark = [&](int k) {
     if (prof) (void)hipEventRecord(prof->ev[k], s);
@@ -746,8 +743,8 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   mark(1);
 
   // Host tables for the rest of the build; everything they hold is known once
-  // the maximum degrees are. They go to the device in one copy, now, while
-  // the device is idle; the core-order sizes themselves are computed there.
+  // the maximum degrees are (the core-order sizes themselves are computed on
+  // the device).
   std::vector<int64_t> hbase(G + 1, 0), Ebase(G + 1, 0), cobase(G + 1, 0), segbase(G + 1, 0), ng(G),
       obase(G + 1, 0);
   for (int32_t g = 0; g < G; ++g) {
@@ -762,24 +759,37 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   const size_t p_hbase = pack.add(hbase), p_Ebase = pack.add(Ebase), p_cobase = pack.add(cobase),
                p_segbase = pack.add(segbase), p_ng = pack.add(ng), p_obase = pack.add(obase),
                p_vbase = pack.add(vbase), p_ebase = pack.add(ebase), p_vt = pack.add(vt), p_rt = pack.add(rt);
-  unsigned char *dpack;
-  SCAN_TRY(pack.upload(*arena, tmp, s, &dpack));
-  const int64_t *d_hbase = pack.at<int64_t>(dpack, p_hbase), *d_Ebase = pack.at<int64_t>(dpack, p_Ebase),
-                *d_cobase = pack.at<int64_t>(dpack, p_cobase), *d_segbase = pack.at<int64_t>(dpack, p_segbase),
-                *d_ng = pack.at<int64_t>(dpack, p_ng), *d_obase = pack.at<int64_t>(dpack, p_obase),
-                *d_vbase = pack.at<int64_t>(dpack, p_vbase), *d_ebase = pack.at<int64_t>(dpack, p_ebase);
-  const VTile *d_vt = pack.at<VTile>(dpack, p_vt);
-  const RTile *d_rt = pack.at<RTile>(dpack, p_rt);
-  int64_t *d_corel;  // per-graph core-order offsets (the indexes' co_off)
-  SCAN_TRY(arena_alloc(*arena, &d_corel, cobase[G]));
+  const int64_t *d_hbase = nullptr, *d_Ebase = nullptr, *d_cobase = nullptr, *d_segbase = nullptr,
+                *d_ng = nullptr, *d_obase = nullptr, *d_vbase = nullptr, *d_ebase = nullptr;
+  const VTile *d_vt = nullptr;
+  const RTile *d_rt = nullptr;
+  int64_t *d_corel = nullptr;  // per-graph core-order offsets (the indexes' co_off)
+  // The tables go to the device in one copy on stream st, and the core-order
+  // offsets are allocated: after the intersection is launched, so that
+  // nothing stands between the read-back above and that launch.
+  auto upload_tables = [&](hipStream_t st) -> scan_status {
+    unsigned char *dpack;
+    SCAN_TRY(pack.upload(*arena, tmp, st, &dpack));
+    d_hbase = pack.at<int64_t>(dpack, p_hbase);
+    d_Ebase = pack.at<int64_t>(dpack, p_Ebase);
+    d_cobase = pack.at<int64_t>(dpack, p_cobase);
+    d_segbase = pack.at<int64_t>(dpack, p_segbase);
+    d_ng = pack.at<int64_t>(dpack, p_ng);
+    d_obase = pack.at<int64_t>(dpack, p_obase);
+    d_vbase = pack.at<int64_t>(dpack, p_vbase);
+    d_ebase = pack.at<int64_t>(dpack, p_ebase);
+    d_vt = pack.at<VTile>(dpack, p_vt);
+    d_rt = pack.at<RTile>(dpack, p_rt);
+    return arena_alloc(*arena, &d_corel, cobase[G]);
+  };
 
   if (NNZ > 0) {
     // a6, first part: core-order sizes and offsets (from the degree
     // histograms, on the device) and the degree-rank list. These read only the
-    // degrees, so they run on a helper stream while the intersection runs;
-    // the host enqueues them once the intersection kernels are launched.
-    hipStream_t cs = helper_stream(2);
-    if (!cs) cs = s;
+    // degrees, so they run on the helper stream that classified the rows (it
+    // is ordered after the degree pass) while the intersection runs; the host
+    // enqueues them once the intersection kernels are launched.
+    const hipStream_t cs = ns ? ns : s;
     JoinOnExit join_cs{s, cs};
     int32_t *d_hist, *d_cursor, *d_sv, *d_tiles_of;
     int64_t *d_E, *d_seg, *d_nz, *d_tile_first, *scan_ws;
@@ -788,6 +798,7 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     SortClasses co_cls;
     const int64_t nrt = (int64_t)rt.size();
     auto co_prep = [&]() -> scan_status {  // cs is ordered after the degrees
+      SCAN_TRY(upload_tables(cs));
       SCAN_TRY(tmp.alloc(&d_hist, hbase[G]));
       SCAN_TRY(tmp.alloc(&d_cursor, hbase[G]));
       SCAN_TRY(tmp.alloc(&d_E, Ebase[G]));
@@ -847,8 +858,7 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       SCAN_TRY(weighted_similarity_all(N, NNZ, off_u, deg, adj_u, w_dev, sims, tmp, s, prof ? &ist : nullptr,
                                        icfg.skip_deg));
     } else {
-      SCAN_TRY(intersect_all(icfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist, cs, co_prep,
-                             &plan));
+      SCAN_TRY(intersect_all(icfg, N, NNZ, off_u, deg, adj_u, kind, sims, counts, device, s, &ist, co_prep, &plan));
     }
     if (lsh) SCAN_TRY(lsh_overwrite(lsh_dev, N, NNZ, off_u, adj_u, weighted ? w_dev : nullptr, kind, sims, tmp, s));
     mark(3);
@@ -857,14 +867,15 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       prof->intersect_launches = ist.launches;
     }
 
-    // a5: neighbour order, then ids made local to each graph.
+    // a5: neighbour order, then ids made local to each graph (with the
+    // tables, which came on the helper stream).
     SCAN_TRY(sort_run(no_cls, off_u, NNZ, sims, adj_u, no_sim, no_ids, s));
+    if (cs != s) SCAN_TRY(stream_wait(s, cs));
     if (G > 1) k_localize_ids<<<grid_for(NNZ, 256), 256, 0, s>>>(no_ids, d_ebase, d_vbase, G, NNZ);
     mark(4);
 
     // a6, second part: transposed fill, segmented sort (after the helper
     // stream's part above).
-    if (cs != s) SCAN_TRY(stream_wait(s, cs));
     if (nrt > 0) {
       k_co_fill<<<grid_for(NNZ / 512 + 1, 1, 1 << 16), 256, 0, s>>>(d_rt, nrt, d_tile_first, d_sv, d_vbase, d_nz,
                                                                     deg, off_u, no_sim, d_corel, d_cobase, d_ebase,
@@ -875,6 +886,7 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     mark(5);
   } else {
     // no edges: every co_off is zero
+    SCAN_TRY(upload_tables(s));
     SCAN_HIP_TRY(hipMemsetAsync(d_corel, 0, (size_t)cobase[G] * 8, s));
     for (int k = 2; k < 10; ++k) mark(k);
   }

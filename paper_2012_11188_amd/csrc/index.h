@@ -57,16 +57,15 @@ scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, c
 
 // a2-a4: ownership plan, then intersection + similarity for every edge,
 // written into both CSR slots of sims (and counts if non-null).
-// side (may be null): a stream ordered after the plan (for work that needs
-// only what precedes the intersection); after_launch (may be empty) runs on
-// the host once every intersection kernel is enqueued, so that the host
-// enqueues other work while the device intersects. plan (may be null: then
-// it plans on s itself) is one made by intersect_plan on s with the same
-// cfg, n, nnz and deg.
+// after_launch (may be empty) runs on the host once every intersection
+// kernel is enqueued, so that the host enqueues other work (on streams it has
+// ordered itself) while the device intersects. plan (may be null: then it
+// plans on s itself) is one made by intersect_plan on s with the same cfg,
+// n, nnz and deg.
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
                           const int32_t *deg, const int32_t *adj, int kind, double *sims,
                           int32_t *counts, int device, hipStream_t s, IntersectStats *stats,
-                          hipStream_t side = nullptr, const std::function<scan_status()> &after_launch = {},
+                          const std::function<scan_status()> &after_launch = {},
                           const IntersectPlan *plan = nullptr);
 
 // Approximate similarities (lsh.hip): k samples, and the random draws on
@@ -142,7 +141,9 @@ struct BuildProfileEvents {
   hipEvent_t ev[10] = {};
   int32_t window_bits = 0;
   int32_t intersect_launches = 0;
-  int32_t *plan_counts = nullptr;  // pinned int32[4], filled in stream order
+  // (light owners, big chunks, -, heavy owners), written by the host when it
+  // reads the plan's counts back
+  int32_t plan_counts[4] = {0, 0, 0, 0};
   ~BuildProfileEvents();
 };
 

@@ -762,11 +762,9 @@ scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, c
 scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
                           const int32_t *deg, const int32_t *adj, int kind, double *sims,
                           int32_t *counts, int device, hipStream_t s, IntersectStats *stats,
-                          hipStream_t side, const std::function<scan_status()> &after_launch,
-                          const IntersectPlan *plan) {
+                          const std::function<scan_status()> &after_launch, const IntersectPlan *plan) {
   if (nnz == 0) {
-    if (side && side != s) SCAN_TRY(stream_wait(side, s));
-    return after_launch ? after_launch() : SCAN_OK;
+      return after_launch ? after_launch() : SCAN_OK;
   }
   int lds_max = 65536, cus = 256;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
@@ -808,7 +806,6 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
     return SCAN_OK;
   };
   SCAN_TRY(mark(stats ? stats->ev_plan_end : nullptr, s));
-  if (side && side != s) SCAN_TRY(stream_wait(side, s));
   // The large-owner kernel is persistent (one 1024-thread workgroup per CU,
   // most of the LDS) and leaves wavefront slots, registers and some LDS free
   // on every CU; the small-owner kernels, independent of it, run on the
