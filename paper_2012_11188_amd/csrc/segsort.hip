@@ -748,15 +748,20 @@ scan_status sort_run(const SortClasses &c, const int64_t *seg_off, int64_t total
   SortStats *st = (SortStats *)c.stats;
   const int32_t *lists = c.lists, *big_tiles_of = c.big_tiles_of;
   const int32_t *cnt = st->count;  // device copies of the class sizes
-  // The big segments' chain of launches (tile sorts, merge passes) runs on
-  // a helper stream, beside the other classes' kernels.
-  hipStream_t bs = s;
+  // The big segments' chain of launches (tile sorts, merge passes) and the
+  // other classes' kernels run beside each other, the longer of the two on s
+  // and the other on a helper stream (the join at the end then waits for the
+  // shorter one, usually already done): the big chain goes on s when the big
+  // segments hold at least half of the elements.
+  hipStream_t bs = s, gs = s;
   if (h.count[kClsBig] && h.count[kClsBig] < nseg) {
     hipStream_t hs = helper_stream(0);
-    if (hs && stream_wait(hs, s) == SCAN_OK) bs = hs;
+    if (hs && stream_wait(hs, s) == SCAN_OK) {
+      if (2 * (int64_t)h.big_tiles * kBigTile >= total) gs = hs;
+      else bs = hs;
+    }
   }
-  JoinOnExit join_bs{s, bs};
-  const hipStream_t gs = s, ms = s;
+  JoinOnExit join_bs{s, bs}, join_gs{s, gs};
   if (h.count[kClsCopy])
     k_sort_copy<<<grid_for(h.count[kClsCopy], 256), 256, 0, gs>>>(seg_off, lists + kClsCopy * nseg, cnt + kClsCopy,
                                                                   key_in, id_in, key_out, id_out);
@@ -774,12 +779,12 @@ scan_status sort_run(const SortClasses &c, const int64_t *seg_off, int64_t total
   if (h.count[C])                                                                              \
     k_sort_block<T, I><<<grid_for(h.count[C], 1), T, 0, ST>>>(seg_off, lists + (C) * nseg, cnt + (C), key_in, \
                                                               id_in, key_out, id_out);
-  SCAN_BLOCK(64, 2, kClsB128, ms)
-  SCAN_BLOCK(64, 4, kClsB256, ms)
-  SCAN_BLOCK(64, 8, kClsB512, ms)
-  SCAN_BLOCK(128, 8, kClsB1024, ms)
-  SCAN_BLOCK(256, 8, kClsB2048, s)
-  SCAN_BLOCK(kSortBlock, kBigTile / kSortBlock, kClsB4096, s)
+  SCAN_BLOCK(64, 2, kClsB128, gs)
+  SCAN_BLOCK(64, 4, kClsB256, gs)
+  SCAN_BLOCK(64, 8, kClsB512, gs)
+  SCAN_BLOCK(128, 8, kClsB1024, gs)
+  SCAN_BLOCK(256, 8, kClsB2048, gs)
+  SCAN_BLOCK(kSortBlock, kBigTile / kSortBlock, kClsB4096, gs)
 #undef SCAN_BLOCK
   if (h.count[kClsBig]) {
     const int32_t nbig = h.count[kClsBig];
