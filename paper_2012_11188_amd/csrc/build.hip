@@ -197,6 +197,12 @@ struct RTile {
   int32_t g;
   int32_t r0;  // first rank (local to graph g)
 };
+// A rank's vertex (union id), its degree and its row offset, written once by
+// the rank pass so that the transpose reads one record per rank.
+struct alignas(16) RankInfo {
+  int32_t v, d;
+  int64_t o;
+};
 
 // Per-graph degree histograms hist_all[hbase[g] + d].
 __global__ __launch_bounds__(256) void k_graph_hist(const VTile *tiles, int64_t ntiles,
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(256) void k_co_rank(const VTile *tiles, int64_t nti
                                                  const int64_t *Ebase, const unsigned *dmax_g,
                                                  const int64_t *E_all, int32_t *cursor_all,
                                                  const int64_t *n_g, const int64_t *svbase,
-                                                 int32_t *sv_all) {
+                                                 const int64_t *off, RankInfo *sv_all) {
   __shared__ int32_t lcnt[kHistBins];
   constexpr int kPer = kRankTile / 256;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256) void k_co_rank(const VTile *tiles, int64_t nti
       if (v >= tl.v1 || lr[k] < 0) continue;
       const int32_t d = deg[v];
       const int64_t r = (n - E[d + 1]) + (d < kHistBins ? lcnt[d] + lr[k] : lr[k]);
-      sv_all[svbase[g] + r] = (int32_t)v;
+      sv_all[svbase[g] + r] = RankInfo{(int32_t)v, d, off[v]};
     }
   }
 }
@@ -308,23 +314,25 @@ __global__ __launch_bounds__(256) void k_co_rank(const VTile *tiles, int64_t nti
 // Number of mu tiles of each rank tile (its first rank has the top degree).
 // Rank tiles are planned from n (known on the host); those past the graph's
 // non-isolated count get no mu tiles.
-__global__ void k_co_tiles(const RTile *rt, int64_t nrt, const int32_t *sv_all,
-                           const int64_t *svbase, const int64_t *nz_g, const int32_t *deg,
-                           int32_t *tiles_of) {
+__global__ void k_co_tiles(const RTile *rt, int64_t nrt, const RankInfo *sv_all,
+                           const int64_t *svbase, const int64_t *nz_g, int32_t *tiles_of) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nrt;
        t += (int64_t)gridDim.x * blockDim.x)
     tiles_of[t] = rt[t].r0 < nz_g[rt[t].g]
-                      ? (deg[sv_all[svbase[rt[t].g] + rt[t].r0]] + kFillMu - 1) / kFillMu
+                      ? (sv_all[svbase[rt[t].g] + rt[t].r0].d + kFillMu - 1) / kFillMu
                       : 0;
 }
 
 // One workgroup per (rank tile, mu tile): kFillRanks consecutive ranks x
 // kFillMu consecutive mu, read row-contiguously from NO_SIM into LDS and
-// written segment-contiguously into the unsorted core order.
-__global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
-                                                 const int64_t *tile_first, const int32_t *sv_all,
+// written segment-contiguously into the unsorted core order. With one graph,
+// rank tile t covers ranks [t kFillRanks, (t + 1) kFillRanks), and the last
+// non-empty rank tiles (low degrees) have one mu tile each, so a block first
+// tries the tile that assumption gives (one read confirms it) before
+// searching.
+__global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt, int32_t one_graph,
+                                                 const int64_t *tile_first, const RankInfo *sv_all,
                                                  const int64_t *svbase, const int64_t *nz_g,
-                                                 const int32_t *deg, const int64_t *off,
                                                  const double *no_sim, const int64_t *co_all,
                                                  const int64_t *cobase, const int64_t *ebase,
                                                  const int64_t *vbase,
@@ -334,28 +342,38 @@ __global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
   __shared__ int64_t vo[kFillRanks];
   __shared__ int64_t s_t, s_k;
   const int64_t total = tile_first[nrt];
+  const int64_t guess_end = one_graph ? (nz_g[0] + kFillRanks - 1) / kFillRanks : 0;
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
     __syncthreads();
     if (threadIdx.x < kWave) {
-      // the last rank tile with tile_first <= b (tile_first[0] = 0): a 64-way
-      // search by the first wavefront, every lane sampling one rank tile
       const int lane = threadIdx.x;
-      int64_t lo = 0, cnt = nrt;
-      while (cnt > 1) {
-        const int64_t step = (cnt + kWave - 1) / kWave;
-        const int64_t q = lo + lane * step;
-        const int c = __popcll(__ballot(q < lo + cnt && tile_first[q] <= b));  // >= 1: lane 0
-        const int64_t nlo = lo + (c - 1) * step;
-        cnt = min(step, lo + cnt - nlo);
-        lo = nlo;
-      }
-      if (lane == 0) {
-        s_t = lo;
-        s_k = b - tile_first[lo];
+      const int64_t guess = guess_end - (total - b);
+      if (one_graph && guess >= 0 && guess < nrt && tile_first[guess] == b) {
+        if (lane == 0) {
+          s_t = guess;
+          s_k = 0;
+        }
+      } else {
+        // the last rank tile with tile_first <= b (tile_first[0] = 0): a
+        // 64-way search by the first wavefront, every lane sampling one tile
+        int64_t lo = 0, cnt = nrt;
+        while (cnt > 1) {
+          const int64_t step = (cnt + kWave - 1) / kWave;
+          const int64_t q = lo + lane * step;
+          const int c = __popcll(__ballot(q < lo + cnt && tile_first[q] <= b));  // >= 1: lane 0
+          const int64_t nlo = lo + (c - 1) * step;
+          cnt = min(step, lo + cnt - nlo);
+          lo = nlo;
+        }
+        if (lane == 0) {
+          s_t = lo;
+          s_k = b - tile_first[lo];
+        }
       }
     }
     __syncthreads();
-    const RTile r = rt[s_t];
+    const int64_t t = s_t;
+    const RTile r = one_graph ? RTile{0, (int32_t)(t * kFillRanks)} : rt[t];
     const int64_t r0 = r.r0;
     const int32_t j0 = (int32_t)(s_k * kFillMu);
     const int64_t *co = co_all + cobase[r.g];  // relative offsets of graph r.g
@@ -363,16 +381,11 @@ __global__ __launch_bounds__(256) void k_co_fill(const RTile *rt, int64_t nrt,
     const int32_t vb = (int32_t)vbase[r.g];
     if (threadIdx.x < kFillRanks) {
       const int64_t rr = r0 + threadIdx.x;
-      int32_t v = 0, d = 0;
-      int64_t o = 0;
-      if (rr < nz_g[r.g]) {
-        v = sv_all[svbase[r.g] + rr];
-        d = deg[v];
-        o = off[v];
-      }
-      vs[threadIdx.x] = v - vb;
-      vd[threadIdx.x] = d;
-      vo[threadIdx.x] = o;
+      RankInfo ri{0, 0, 0};
+      if (rr < nz_g[r.g]) ri = sv_all[svbase[r.g] + rr];
+      vs[threadIdx.x] = ri.v - vb;
+      vd[threadIdx.x] = ri.d;
+      vo[threadIdx.x] = ri.o;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kFillRanks * kFillMu; e += blockDim.x) {
@@ -650,7 +663,7 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
   // a2: the ownership plan needs only the degrees; its counts come back with
   // the maximum degrees below.
   IntersectPlan plan;
-  if (NNZ > 0 && !weighted) SCAN_TRY(intersect_plan(cfg, N, NNZ, deg, tmp, s, plan));
+  if (NNZ > 0 && !weighted) SCAN_TRY(intersect_plan(cfg, N, NNZ, off_u, deg, adj_u, device, tmp, s, plan));
   // The small-owner kernels' helper streams wait for the plan now, off the
   // path between the read-back and the first intersection launch.
   JoinOnExit join_h0{s, nullptr}, join_h1{s, nullptr};
@@ -791,7 +804,8 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     // enqueues them once the intersection kernels are launched.
     const hipStream_t cs = ns ? ns : s;
     JoinOnExit join_cs{s, cs};
-    int32_t *d_hist, *d_cursor, *d_sv, *d_tiles_of;
+    int32_t *d_hist, *d_cursor, *d_tiles_of;
+    RankInfo *d_sv;
     int64_t *d_E, *d_seg, *d_nz, *d_tile_first, *scan_ws;
     double *co_key;
     int32_t *co_id;
@@ -830,9 +844,9 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
       if (!vt.empty())
         k_co_rank<<<grid_for((int64_t)vt.size(), 1, 8192), 256, 0, cs>>>(d_vt, (int64_t)vt.size(), deg, d_hbase,
                                                                        d_Ebase, d_dmax, d_E, d_cursor, d_ng, d_vbase,
-                                                                       d_sv);
+                                                                       off_u, d_sv);
       if (nrt > 0) {
-        k_co_tiles<<<grid_for(nrt, 256), 256, 0, cs>>>(d_rt, nrt, d_sv, d_vbase, d_nz, deg, d_tiles_of);
+        k_co_tiles<<<grid_for(nrt, 256), 256, 0, cs>>>(d_rt, nrt, d_sv, d_vbase, d_nz, d_tiles_of);
         SCAN_TRY(exclusive_scan(d_tiles_of, d_tile_first, nrt, scan_ws, cs));
       }
       return sort_classify(d_seg, segbase[G], tmp, cs, co_cls);  // the core-order segments
@@ -877,9 +891,9 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     // a6, second part: transposed fill, segmented sort (after the helper
     // stream's part above).
     if (nrt > 0) {
-      k_co_fill<<<grid_for(NNZ / 512 + 1, 1, 1 << 16), 256, 0, s>>>(d_rt, nrt, d_tile_first, d_sv, d_vbase, d_nz,
-                                                                    deg, off_u, no_sim, d_corel, d_cobase, d_ebase,
-                                                                    d_vbase, co_key, co_id);
+      k_co_fill<<<grid_for(NNZ / 512 + 1, 1, 1 << 16), 256, 0, s>>>(d_rt, nrt, G == 1 ? 1 : 0, d_tile_first, d_sv,
+                                                                    d_vbase, d_nz, no_sim, d_corel, d_cobase,
+                                                                    d_ebase, d_vbase, co_key, co_id);
     }
     SCAN_TRY(sort_run(co_cls, d_seg, NNZ, co_key, co_id, co_thr, co_ids, s));
     SCAN_HIP_TRY(hipGetLastError());

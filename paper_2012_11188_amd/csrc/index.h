@@ -47,13 +47,16 @@ struct IntersectPlan {
   // helper streams already ordered after the plan (set by the caller), used
   // for the two small-owner kernels; null: intersect_all orders its own
   hipStream_t helper[2] = {nullptr, nullptr};
+  int32_t wbits = 0;       // the large-owner kernel's id window width
+  int32_t *wt = nullptr;   // window table (ids over several windows), or null
   IntersectPlan() = default;
   IntersectPlan(const IntersectPlan &) = delete;
   IntersectPlan &operator=(const IntersectPlan &) = delete;
   ~IntersectPlan();
 };
-scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int32_t *deg,
-                           DevArena &arena, hipStream_t s, IntersectPlan &plan);
+scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
+                           const int32_t *deg, const int32_t *adj, int device, DevArena &arena, hipStream_t s,
+                           IntersectPlan &plan);
 
 // a2-a4: ownership plan, then intersection + similarity for every edge,
 // written into both CSR slots of sims (and counts if non-null).

@@ -694,17 +694,57 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
 // Window table of every row: wt[u * (nwin + 1) + k] = the first position in
 // row u whose id is >= k * 2^wbits (k = 0..nwin), so that a lower
 // neighbour's ids inside window k are positions [wt[k], wt[k + 1]) of its
-// row. One wavefront per row, 64 ids per step: a lane whose id opens
-// windows past its left neighbour's writes their starts (every entry is
-// written once); the step past the row's end closes the last windows.
+// row. One wavefront per row; the next row's offsets are requested while a
+// row is handled. Rows of up to kTableScan ids are streamed 64 ids per step:
+// a lane whose id opens windows past its left neighbour's writes their
+// starts (every entry is written once), and the step past the row's end
+// closes the last windows. Longer rows find each window's start by a 64-way
+// search (every lane samples one position, a few rounds per window), so that
+// no wavefront walks a hub's whole row.
+constexpr int32_t kTableScan = 2048;
+
 __global__ __launch_bounds__(256) void k_window_table(const int64_t *off, const int32_t *adj, int64_t n,
                                                       int wbits, int32_t nwin, int32_t *wt) {
   const int lane = lane_id();
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; u < n; u += nw) {
-    const int64_t o = off[u];
-    const int32_t d = (int32_t)(off[u + 1] - o);
+  int64_t u = uniform64((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  int64_t o_next = 0, e_next = 0;  // offsets of the wavefront's next row
+  if (u < n) {
+    o_next = off[u];
+    e_next = off[u + 1];
+  }
+  for (; u < n; u += nw) {
+    const int64_t o = uniform64(o_next);
+    const int32_t d = uniform((int32_t)(uniform64(e_next) - o));
+    if (u + nw < n) {
+      o_next = off[u + nw];
+      e_next = off[u + nw + 1];
+    }
     int32_t *t = wt + u * (nwin + 1);
+    if (d > kTableScan) {
+      int32_t lo = 0;  // window starts do not decrease with k
+      for (int32_t k = 1; k < nwin; ++k) {
+        const int64_t bound = (int64_t)k << wbits;
+        int32_t hi = d;  // the start is in [lo, hi]; position d stands for the end of the row
+        while (lo < hi) {
+          // (kWave - 1) * step >= hi - lo: the last lane samples at or past hi
+          const int32_t step = (hi - lo + kWave - 2) / (kWave - 1);
+          const int64_t p = (int64_t)lo + (int64_t)lane * step;
+          const bool at = p >= hi || adj[o + p] >= bound;
+          const int f = __ffsll((unsigned long long)__ballot(at)) - 1;  // >= 0: the last lane is true
+          if (f == 0) break;  // the start is lo
+          const int32_t nlo = lo + (f - 1) * step + 1;
+          hi = uniform((int32_t)min((int64_t)hi, (int64_t)lo + (int64_t)f * step));
+          lo = uniform(nlo);
+        }
+        if (lane == 0) t[k] = lo;
+      }
+      if (lane == 0) {
+        t[0] = 0;
+        t[nwin] = d;
+      }
+      continue;
+    }
     int32_t prev = -1;  // window of the id before this step (wave-uniform)
     for (int32_t i0 = 0; i0 <= d; i0 += kWave) {
       const int32_t i = i0 + lane;
@@ -734,12 +774,36 @@ IntersectPlan::~IntersectPlan() {
   pinned_put(host);
 }
 
-scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int32_t *deg,
-                           DevArena &arena, hipStream_t s, IntersectPlan &p) {
+// The id window width of the large-owner kernel: cfg.wbits, no wider than
+// the id space and narrowed until its LDS fits.
+static int window_bits(const IntersectConfig &cfg, int64_t n, int lds_max) {
+  int wbits = cfg.wbits;
+  int nb = 0;
+  while (((int64_t)1 << nb) < n) ++nb;
+  if (nb < 10) nb = 10;
+  if (wbits > nb) wbits = nb;
+  while (wbits > 10 && big_lds_bytes(wbits, cfg.spc) > (size_t)lds_max) --wbits;
+  return wbits;
+}
+
+scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, const int64_t *off,
+                           const int32_t *deg, const int32_t *adj, int device, DevArena &arena, hipStream_t s,
+                           IntersectPlan &p) {
   static_assert(sizeof(PlanCounts) <= kPinnedBlock, "plan counts fit a pinned block");
   p.n = n;
   p.nnz = nnz;
   if (nnz == 0) return SCAN_OK;
+  // Ids spanning several windows: the window table goes first (it needs
+  // only the CSR), so that the large-owner kernel can start as soon as the
+  // host has read the plan's counts.
+  int lds_max = 65536;
+  (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  p.wbits = window_bits(cfg, n, lds_max);
+  const int32_t nwin = (int32_t)((n + ((int64_t)1 << p.wbits) - 1) >> p.wbits);
+  if (nwin > 1 && !cfg.search_windows && (size_t)(nwin + 1) * (size_t)n * 4 <= kMaxWindowTable) {
+    SCAN_TRY(arena.alloc(&p.wt, (int64_t)(nwin + 1) * n));
+    k_window_table<<<grid_for(n * kWave, 256), 256, 0, s>>>(off, adj, n, p.wbits, nwin, p.wt);
+  }
   BigChunk *big_list;
   PlanCounts *pc;
   SCAN_TRY(arena.alloc(&p.small_list, n));
@@ -769,21 +833,17 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   int lds_max = 65536, cus = 256;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  int wbits = cfg.wbits;
-  int nb = 0;
-  while (((int64_t)1 << nb) < n) ++nb;
-  if (nb < 10) nb = 10;
-  if (wbits > nb) wbits = nb;  // no wider than the id space
-  while (wbits > 10 && big_lds_bytes(wbits, cfg.spc) > (size_t)lds_max) --wbits;
+  const int wbits = window_bits(cfg, n, lds_max);
   if (big_lds_bytes(wbits, cfg.spc) > (size_t)lds_max) return fail(SCAN_EINVAL, "chunk size too large for LDS");
 
   DevArena tmp(s);
   IntersectPlan own;
   if (!plan) {
-    SCAN_TRY(intersect_plan(cfg, n, nnz, deg, tmp, s, own));
+    SCAN_TRY(intersect_plan(cfg, n, nnz, off, deg, adj, device, tmp, s, own));
     plan = &own;
   }
-  if (plan->n != n || plan->nnz != nnz || !plan->ready) return fail(SCAN_EINVAL, "plan made for another graph");
+  if (plan->n != n || plan->nnz != nnz || !plan->ready || plan->wbits != wbits)
+    return fail(SCAN_EINVAL, "plan made for another graph");
   const int32_t *small_list = plan->small_list, *heavy_list = plan->heavy_list;
   const BigChunk *big_list = (const BigChunk *)plan->big_list;
   PlanCounts *pc = (PlanCounts *)plan->counts;
@@ -825,15 +885,11 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   if (h.big) {
     size_t lds = big_lds_bytes(wbits, cfg.spc);
     const bool one = n <= ((int64_t)1 << wbits);
-    // Several windows: each row's window starts come from a table (one
-    // pass over adj) unless it would exceed kMaxWindowTable bytes or the
-    // searched ranges are asked for; then chunks search them per window.
-    int32_t *wt = nullptr;
+    // Several windows: each row's window starts come from the plan's table
+    // unless it would exceed kMaxWindowTable bytes or the searched ranges are
+    // asked for; then chunks search them per window.
+    int32_t *wt = plan->wt;
     const int32_t nwin = (int32_t)((n + ((int64_t)1 << wbits) - 1) >> wbits);
-    if (!one && !cfg.search_windows && (size_t)(nwin + 1) * (size_t)n * 4 <= kMaxWindowTable) {
-      SCAN_TRY(tmp.alloc(&wt, (int64_t)(nwin + 1) * n));
-      k_window_table<<<grid_for(n * kWave, 256), 256, 0, s>>>(off, adj, n, wbits, nwin, wt);
-    }
     const void *fn = one ? (const void *)k_big_owner<true> : (const void *)k_big_owner<false>;
     hipFuncAttributes fa;
     SCAN_HIP_TRY(hipFuncGetAttributes(&fa, fn));
