@@ -168,7 +168,7 @@ def autotune(scan, graphs, kind, tune_arg, reps=2):
         return full, {"source": "given"}
     t0 = time.perf_counter()
     best = scan.scan_autotune(graphs, kind, reps=reps)
-    info = {"source": "autotuner", "search_s": time.perf_counter() - t0, "intersect_ms": best["ms"]}
+    info = {"source": "autotuner", "search_s": time.perf_counter() - t0, "through_intersect_ms": best["ms"]}
     log(f"autotune: {best} in {info['search_s']:.1f}s")
     return {k: best[k] for k in ("small_max", "spc", "wbits")}, info
 

@@ -71,10 +71,11 @@ enum {
 /* Per-phase device times of a build made with SCAN_PROFILE, in milliseconds,
  * from hipEvents recorded on the build stream between phases:
  *   prepare     degrees, offsets, max degree (and validation if asked),
- *               the edge-ownership plan (chunk lists per table class) and
- *               the read-back of both
- *   plan        host tables of the later phases, up to the first
- *               intersection launch (the device is idle here)
+ *               the per-row window table (when ids span several bitmap
+ *               windows), the edge-ownership plan (chunk lists per table
+ *               class) and the read-back of the max degree and plan counts
+ *   plan        from that read-back to the first intersection launch (the
+ *               device is idle here)
  *   intersect   all intersection + similarity launches, split into
  *               intersect_small (owners of degree <= small_max, one
  *               wavefront each) and intersect_big (bitmap-window owners)
@@ -265,12 +266,13 @@ scan_status scan_build_index_ex(const scan_csr *gs, int32_t count, scan_sim_kind
                                 uint32_t flags, const scan_tune *tune, void *stream,
                                 scan_index **outs);
 
-/* Autotuner: times the intersection phase of builds of gs (count graphs,
- * merged as in scan_build_index_batch) over a coordinate sweep of scan_tune
- * (small_max, then spc, then wbits; each candidate run `reps` times, the
- * minimum kept) and writes the fastest setting to *best and its intersection
- * time to *best_ms (may be NULL). Synchronous; builds and frees temporary
- * indexes on `stream`. reps in 1..16. */
+/* Autotuner: times the phases of builds of gs (count graphs, merged as in
+ * scan_build_index_batch) up to the end of the intersection (prepare, which
+ * holds the ownership plan and any window table, plan and intersect) over a
+ * coordinate sweep of scan_tune (small_max, then spc, then wbits; each
+ * candidate run `reps` times, the minimum kept) and writes the fastest
+ * setting to *best and that time to *best_ms (may be NULL). Synchronous;
+ * builds and frees temporary indexes on `stream`. reps in 1..16. */
 scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind, int32_t reps,
                           void *stream, scan_tune *best, float *best_ms);
 

@@ -322,7 +322,8 @@ scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind,
   if (reps < 1 || reps > 16) return fail(SCAN_EINVAL, "reps must be in 1..16");
   const hipStream_t s = (hipStream_t)stream;
   std::vector<scan_index *> outs(count, nullptr);
-  // Plan + intersection time of one build with cfg (minimum over reps).
+  // Time of one build with cfg up to the end of the intersection (minimum
+  // over reps).
   auto time_cfg = [&](const IntersectConfig &cfg, float *ms) -> scan_status {
     float bt = INFINITY;
     for (int32_t r = 0; r < reps; ++r) {
@@ -334,7 +335,7 @@ scan_status scan_autotune(const scan_csr *gs, int32_t count, scan_sim_kind kind,
         o = nullptr;
       }
       SCAN_TRY(st);
-      bt = std::min(bt, (float)(prof.plan_ms + prof.intersect_ms));
+      bt = std::min(bt, (float)(prof.prepare_ms + prof.plan_ms + prof.intersect_ms));
     }
     *ms = bt;
     return SCAN_OK;
