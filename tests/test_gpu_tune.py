@@ -99,3 +99,34 @@ def test_tune_tiny_bitmap_owners(seed):
         ix = scan.scan_build_index(*device_csr(g), kind, FLAGS, tune={"small_max": 1, "spc": 4})
         torch.cuda.synchronize()
         assert_index_equal(ix, oix, g)
+
+
+def test_window_table_long_rows():
+    """Rows longer than the window table's streaming limit (2,048 ids), with
+    ids over many bitmap windows: two hubs whose rows cross every window
+    boundary, one whose ids skip most windows (empty ranges between and
+    after), and a sparse background, at 10-bit windows (12 of them)."""
+    import torch
+
+    rng = np.random.default_rng(2012)
+    n = 12_000
+    edges = set()
+    def add(u, v):
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    for h, m in ((0, 5000), (7000, 3000)):  # rows of 5,000 and 3,000 ids across all windows
+        for v in rng.choice(n, size=m, replace=False):
+            add(h, int(v))
+    for v in np.concatenate([rng.choice(2048, size=1900, replace=False), rng.choice(1024, size=900, replace=False) + 9 * 1024]):
+        add(11_999, int(v))  # ids in windows 0, 1 and 9 only
+    for u, v in rng.integers(0, n, size=(40_000, 2)):
+        add(int(u), int(v))
+    g = graphgen.from_edges(n, sorted(edges))
+    assert (np.diff(g.off) > 2048).sum() == 3
+    for kind in (scan.COSINE, scan.JACCARD):
+        oix = oracle.build_index(g, kind, threads=8)
+        for tune in ({"wbits": 10, "spc": 256}, {"wbits": 10, "spc": 64, "small_max": 16}, {"wbits": 11}):
+            print("kind", kind, "tune", tune, flush=True)
+            ix = scan.scan_build_index(*device_csr(g, 64), kind, FLAGS, tune=tune)
+            torch.cuda.synchronize()
+            assert_index_equal(ix, oix, g)
