@@ -12,11 +12,12 @@
 //   v's sketch is the least perm[x] over x in N[v] in bin b (0xffffffff when
 //   none). Estimate: matching non-empty bins / (k - bins empty in both).
 //
-//   k_simhash_big  one workgroup per (high vertex, group of 64 directions):
-//                its wavefronts gather the coordinates of kShChunk row
-//                entries into LDS, then one of them adds them in ascending x
-//                (lane i: direction g * 64 + i); the signs form one 64-bit
-//                word by ballot.
+//   k_simhash_big  workgroups resident on every CU claim (high vertex, group
+//                of 64 directions) items from a counter; per item its
+//                wavefronts gather the coordinates of kShChunk row entries
+//                into LDS, then one of them adds them in ascending x (lane i:
+//                direction g * 64 + i); the signs form one 64-bit word by
+//                ballot.
 //   k_minhash    one wavefront per high vertex: k bins in LDS, atomicMin of
 //                perm[x] over N[v].
 //   k_estimate   one wavefront per piece of 64 slots of a high vertex's row
@@ -36,7 +37,7 @@ namespace {
 constexpr int kLshThreads = 256;
 constexpr int kLshWaves = kLshThreads / kWave;
 constexpr int kLshPiece = 64;  // row slots per estimate work item
-constexpr int kShChunk = 128;    // row entries staged in LDS per round of the block kernel
+constexpr int kShChunk = 64;     // row entries staged in LDS per round of the block kernel
 constexpr int kShThreads = 256;
 constexpr int kShUnroll = 8;     // entries whose LDS values the summing wave reads ahead
 constexpr int kShWaves = kShThreads / kWave;
@@ -63,20 +64,30 @@ __global__ void k_simhash_list(const int64_t *off, int64_t n, int32_t k, int32_t
 }
 
 // SimHash words, words[v * (k / 64) + g] with bit i for direction g * 64 + i:
-// one workgroup per (high vertex, group of 64 directions). Per round, all waves gather the coordinates of kShChunk row
-// entries into LDS (a wave's gathers are issued back to back, so hundreds
-// are in flight at once), then wave 0 adds them in ascending order, lane i
-// for direction g * 64 + i, with the self term at its place.
+// one item per (high vertex, group of 64 directions). The grid is what the
+// CUs hold at once, and each workgroup claims its next item from *claim as
+// soon as it is done (item sizes follow the degrees, so a static split would
+// leave most workgroups idle behind the longest lists). Per round, all waves
+// gather the coordinates of kShChunk row entries into LDS (a wave's gathers
+// are issued back to back, so hundreds are in flight at once), then wave 0
+// adds them in ascending order, lane i for direction g * 64 + i, with the
+// self term at its place.
 __global__ __launch_bounds__(kShThreads) void k_simhash_big(const int64_t *off, const int32_t *adj, const double *w,
                                                             const double *gauss, int32_t k, const int32_t *big,
-                                                            const int32_t *nbig, uint64_t *words) {
+                                                            const int32_t *nbig, unsigned long long *claim,
+                                                            uint64_t *words) {
   extern __shared__ double st[];           // [kShChunk][64] coordinates
   __shared__ int32_t sid[kShChunk];        // the entries' ids
   __shared__ double sw[kShChunk];          // and weights
+  __shared__ int64_t s_item;
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int32_t groups = k / kWave;
   const int64_t items = (int64_t)uniform(*nbig) * groups;
-  for (int64_t t = blockIdx.x; t < items; t += gridDim.x) {
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(claim, 1ull);
+    __syncthreads();
+    const int64_t t = s_item;
+    if (t >= items) break;  // uniform across the block
     const int64_t v = big[t / groups];
     const int32_t g = (int32_t)(t % groups);
     const int64_t o = uniform64(off[v]), d = uniform64(off[v + 1]) - o;
@@ -130,6 +141,7 @@ __global__ __launch_bounds__(kShThreads) void k_simhash_big(const int64_t *off, 
       const uint64_t bits = __ballot(acc >= 0.0);
       if (lane == 0) words[v * groups + g] = bits;
     }
+    __syncthreads();  // every thread has read s_item before the next claim
   }
 }
 
@@ -265,13 +277,25 @@ scan_status lsh_overwrite(const LshSpec &spec, int64_t n, int64_t nnz, const int
     SCAN_HIP_TRY(hipMemcpyAsync(table, t.data(), t.size() * 8, hipMemcpyHostToDevice, s));
     SCAN_TRY(tmp.alloc(&words, n * (int64_t)(k / kWave)));
     int32_t *big, *nbig;
+    unsigned long long *claim;
     SCAN_TRY(tmp.alloc(&big, n));
     SCAN_TRY(tmp.alloc(&nbig, 1));
+    SCAN_TRY(tmp.alloc(&claim, 1));
     SCAN_HIP_TRY(hipMemsetAsync(nbig, 0, 4, s));
+    SCAN_HIP_TRY(hipMemsetAsync(claim, 0, 8, s));
     k_simhash_list<<<grid_for(n, 256), 256, 0, s>>>(off, n, k, big, nbig);
     const size_t lds = (size_t)kShChunk * kWave * 8;
     SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_simhash_big, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    k_simhash_big<<<1024, kShThreads, lds, s>>>(off, adj, w, spec.gauss, k, big, nbig, words);
+    int device = 0, cus = 256, per_cu = 0;
+    (void)hipGetDevice(&device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_simhash_big, kShThreads, lds) !=
+            hipSuccess ||
+        per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+    }
+    k_simhash_big<<<cus * per_cu, kShThreads, lds, s>>>(off, adj, w, spec.gauss, k, big, nbig, claim, words);
   }
   int32_t *cnt;
   int64_t *P, *ws;
