@@ -19,9 +19,11 @@
 //                    unweighted path). The owner's ids and weights go into LDS
 //                    in tiles of kWTile; every lower neighbour l streams its
 //                    row through them in ascending order, a lane finds its id
-//                    by binary search in the tile, and the wavefront adds the
-//                    products of the common ids in ascending id, inserting the
-//                    terms of x = h (1 * w(l, h)) and x = l (w(h, l) * 1).
+//                    by binary search in its bucket of the tile (kWBuckets
+//                    buckets of equal id width, indexed per tile), and the
+//                    wavefront adds the products of the common ids in
+//                    ascending id, inserting the terms of x = h (1 * w(l, h))
+//                    and x = l (w(h, l) * 1).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -35,6 +37,7 @@ constexpr int kWUnit = 128;                  // CSR slots per workgroup
 constexpr int kWThreads = 256;
 constexpr int kWWaves = kWThreads / kWave;
 constexpr int kWTile = 1024;                 // owner ids (and weights) per LDS tile
+constexpr int kWBuckets = 512;               // id buckets per tile (a lookup's first guess)
 constexpr int kWRows = 64;                   // row offsets staged at a time
 #ifndef SCAN_W_CHUNKS
 #define SCAN_W_CHUNKS 4
@@ -111,6 +114,7 @@ __global__ void k_w_unit_rows(const int64_t *off, int64_t n, int32_t *row_of) {
 struct WShared {
   int32_t tid[kWTile];      // the owner's ids of the current tile
   double tw[kWTile];        // and their weights w(h, x)
+  int32_t bst[kWBuckets + 1];  // first tile position of each id bucket (then tn)
   int64_t roff[kWRows + 1];  // off[base .. base + kWRows]
   int64_t lou[kWUnit];      // row offset of the j-th lower neighbour
   double acc[kWUnit];       // its running dot product
@@ -186,7 +190,21 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
           sh.tw[i] = w[ra + t0 + i];
         }
         __syncthreads();
-        const int32_t hi = uniform(sh.tid[tn - 1]);
+        const int32_t tlo = uniform(sh.tid[0]), hi = uniform(sh.tid[tn - 1]);
+        // Buckets of 2^tsh ids from tlo: bucket b holds positions
+        // [bst[b], bst[b + 1]) (every entry written once, by the position
+        // that opens it, or by the last position for the empty tail).
+        int tsh = 0;
+        while (((hi - tlo) >> tsh) >= kWBuckets) ++tsh;
+        const int32_t nb = ((hi - tlo) >> tsh) + 1;
+        for (int i = threadIdx.x; i < tn; i += blockDim.x) {
+          const int32_t bi = (sh.tid[i] - tlo) >> tsh;
+          const int32_t bp = i > 0 ? (sh.tid[i - 1] - tlo) >> tsh : -1;
+          for (int32_t b = bp + 1; b <= bi; ++b) sh.bst[b] = i;
+          if (i == tn - 1)
+            for (int32_t b = bi + 1; b <= nb; ++b) sh.bst[b] = tn;
+        }
+        __syncthreads();
         const bool last = t0 + kWTile >= dh;
         for (int32_t j = wave; j < nlow; j += kWWaves) {
           if (!last && uniform(sh.nxt[j]) > hi) continue;  // nothing of l's row up to hi is left
@@ -203,7 +221,14 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
             const int32_t x = in ? xq : INT_MAX;
             const double wl = in ? wq : 0.0;
             const bool valid = in && (last || x <= hi);
-            int32_t lo = 0, len = tn;  // lower_bound of x in the tile
+            // lower_bound of x in its bucket (x outside [tlo, hi]: no hit)
+            const bool inr = x >= tlo && x <= hi;
+            int32_t lo = 0, len = 0;
+            if (inr) {
+              const int32_t b = (x - tlo) >> tsh;
+              lo = sh.bst[b];
+              len = sh.bst[b + 1] - lo;
+            }
             while (len > 0) {
               const int32_t half = len >> 1;
               if (sh.tid[lo + half] < x) {
@@ -213,7 +238,7 @@ __global__ __launch_bounds__(kWThreads) void k_w_owner(const int64_t *off, const
                 len = half;
               }
             }
-            const bool hit = valid && lo < tn && sh.tid[lo] == x;
+            const bool hit = valid && inr && lo < tn && sh.tid[lo] == x;
             const bool selfh = valid && x == (int32_t)h;
             const double prod = hit ? sh.tw[lo] * wl : wl;  // x = h: w(h, h) = 1
             const int cnt = __popcll(__ballot(valid));      // the valid lanes are a prefix
