@@ -123,12 +123,26 @@ __global__ __launch_bounds__(kPrepThreads) void k_union_prepare(const GraphDesc 
 }
 
 // Vertex ids in [lo, hi) slots of the union made local: id - vbase(g).
+// A thread takes kLocalizePer consecutive slots: one search for the first
+// slot's graph, then a step to the next graph where a slot passes its end.
+constexpr int kLocalizePer = 16;
+
 __global__ void k_localize_ids(int32_t *ids, const int64_t *ebase, const int64_t *vbase, int G,
                                int64_t nnz) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nnz;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    const int g = find_graph(ebase, G, s);
-    ids[s] -= (int32_t)vbase[g];
+  for (int64_t s0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * kLocalizePer; s0 < nnz;
+       s0 += (int64_t)gridDim.x * blockDim.x * kLocalizePer) {
+    int g = find_graph(ebase, G, s0);
+    int64_t end = ebase[g + 1];
+    int32_t vb = (int32_t)vbase[g];
+    const int64_t s1 = s0 + kLocalizePer < nnz ? s0 + kLocalizePer : nnz;
+    for (int64_t s = s0; s < s1; ++s) {
+      while (s >= end) {  // graphs without edges are stepped over
+        ++g;
+        end = ebase[g + 1];
+        vb = (int32_t)vbase[g];
+      }
+      ids[s] -= vb;
+    }
   }
 }
 
@@ -885,7 +899,8 @@ scan_status build_index_batch(const scan_csr *gs, int32_t G, int32_t kind, uint3
     // tables, which came on the helper stream).
     SCAN_TRY(sort_run(no_cls, off_u, NNZ, sims, adj_u, no_sim, no_ids, s));
     if (cs != s) SCAN_TRY(stream_wait(s, cs));
-    if (G > 1) k_localize_ids<<<grid_for(NNZ, 256), 256, 0, s>>>(no_ids, d_ebase, d_vbase, G, NNZ);
+    if (G > 1)
+      k_localize_ids<<<grid_for(NNZ / kLocalizePer + 1, 256), 256, 0, s>>>(no_ids, d_ebase, d_vbase, G, NNZ);
     mark(4);
 
     // a6, second part: transposed fill, segmented sort (after the helper

@@ -704,7 +704,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_owner(
 constexpr int32_t kTableScan = 2048;
 
 __global__ __launch_bounds__(256) void k_window_table(const int64_t *off, const int32_t *adj, int64_t n,
-                                                      int wbits, int32_t nwin, int32_t *wt) {
+                                                      int wbits, int32_t nwin, const PlanCounts *pc, int32_t *wt) {
+  if (pc->big == 0) return;  // no bitmap owners: the table is not read
   const int lane = lane_id();
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   int64_t u = uniform64((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -793,17 +794,10 @@ scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, c
   p.n = n;
   p.nnz = nnz;
   if (nnz == 0) return SCAN_OK;
-  // Ids spanning several windows: the window table goes first (it needs
-  // only the CSR), so that the large-owner kernel can start as soon as the
-  // host has read the plan's counts.
   int lds_max = 65536;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
   p.wbits = window_bits(cfg, n, lds_max);
   const int32_t nwin = (int32_t)((n + ((int64_t)1 << p.wbits) - 1) >> p.wbits);
-  if (nwin > 1 && !cfg.search_windows && (size_t)(nwin + 1) * (size_t)n * 4 <= kMaxWindowTable) {
-    SCAN_TRY(arena.alloc(&p.wt, (int64_t)(nwin + 1) * n));
-    k_window_table<<<grid_for(n * kWave, 256), 256, 0, s>>>(off, adj, n, p.wbits, nwin, p.wt);
-  }
   BigChunk *big_list;
   PlanCounts *pc;
   SCAN_TRY(arena.alloc(&p.small_list, n));
@@ -820,6 +814,14 @@ scan_status intersect_plan(const IntersectConfig &cfg, int64_t n, int64_t nnz, c
                                                                              p.small_list, p.heavy_list, big_list, pc);
   SCAN_HIP_TRY(hipMemcpyAsync(p.host, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
   SCAN_HIP_TRY(hipEventRecord(p.ready, s));
+  // Ids spanning several windows: the window table follows the plan (it
+  // needs only the CSR, and nothing when there are no bitmap owners), so
+  // that the large-owner kernel can start as soon as the host has read the
+  // plan's counts.
+  if (nwin > 1 && !cfg.search_windows && (size_t)(nwin + 1) * (size_t)n * 4 <= kMaxWindowTable) {
+    SCAN_TRY(arena.alloc(&p.wt, (int64_t)(nwin + 1) * n));
+    k_window_table<<<grid_for(n * kWave, 256), 256, 0, s>>>(off, adj, n, p.wbits, nwin, pc, p.wt);
+  }
   return SCAN_OK;
 }
 
