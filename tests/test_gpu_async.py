@@ -80,3 +80,28 @@ def test_free_before_finish_and_host_inputs():
     del off, adj
     torch.cuda.synchronize()
     assert_index_equal(ix, oix, g)
+
+
+def test_batches_on_two_streams_with_profiling():
+    """Merged builds (several graphs, tables uploaded on a helper stream, ids
+    made local per graph) enqueued on two streams back to back, profiled,
+    with the first batch's indexes freed before the device has finished:
+    every index of the second batch equals the oracle's."""
+    import torch
+
+    gs = [graphgen.rmat(12, 16, seed=40 + i) for i in range(3)] + [graphgen.sbm(3000, 6, 0.04, 0.002, seed=7)]
+    oix = [oracle.build_index(g, oracle.JACCARD, threads=8) for g in gs]
+    dev = [device_csr(g, 64 if i % 2 else 32) for i, g in enumerate(gs)]
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    flags = FLAGS | scan.SCAN_PROFILE
+    with torch.cuda.stream(sa):
+        first = scan.scan_build_index_batch(dev[::-1], scan.JACCARD, flags, stream=sa)
+    with torch.cuda.stream(sb):
+        second = scan.scan_build_index_batch(dev, scan.JACCARD, flags, stream=sb)
+    for ix in first:
+        ix.free()
+    torch.cuda.synchronize()
+    for g, o, ix in zip(gs, oix, second):
+        p = scan.scan_index_build_profile(ix)
+        assert p["total_ms"] > 0
+        assert_index_equal(ix, o, g)
