@@ -201,10 +201,22 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t x, int tbits) {
   return ((uint32_t)x * 2654435761u) >> (32 - tbits);  // Fibonacci hashing
 }
 
-// LDS bytes of k_small_owner for a given small_max.
-static inline size_t small_lds_bytes(int small_max) {
+// Hash table slots per row entry (at least), the kernels' `spread`: the load
+// factor is at most 1 / spread. A wavefront's probe loop runs as long as its
+// longest chain, so sparse tables pay, up to the LDS they take from other
+// workgroups. Builds of the 256-graph SBM batch (light owners, no bitmap
+// kernel beside them) took 59.8, 53.0 and 50.8 ms with spreads of 2, 4 and 8;
+// R-MAT-23 (heavy owners) 455.4, 452.6 and 454.9 ms. R-MAT-20, whose light
+// owners run beside the bitmap kernel, took 7.06 ms per step with a light
+// spread of 4 and 7.11 ms with 8. So the heavy kernel takes 4 (which also
+// keeps small_max = 4096 within the LDS) and the light one 4 beside the
+// bitmap kernel, else 8.
+constexpr int kSpreadHeavy = 4, kSpreadLight = 4, kSpreadLightAlone = 8;
+
+// LDS bytes of k_small_owner for a given small_max and spread.
+static inline size_t small_lds_bytes(int small_max, int spread) {
   int tb = 6;
-  while ((1 << tb) < 2 * small_max) ++tb;
+  while ((1 << tb) < spread * small_max) ++tb;
   return (size_t)small_max * 20 + ((size_t)4 << tb);
 }
 
@@ -212,7 +224,7 @@ static inline size_t small_lds_bytes(int small_max) {
 // claim entries from a counter. The count is read from device memory.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
-    const int32_t *list, const int32_t *countp, int32_t *claim, int small_max, const int64_t *off,
+    const int32_t *list, const int32_t *countp, int32_t *claim, int small_max, int spread, const int64_t *off,
     const int32_t *deg, const int32_t *adj, int kind, double *sims, int32_t *counts, int32_t skip) {
   const int32_t count = *countp;
   __shared__ int32_t s_idx;
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_small_owner(
     const int32_t dh = deg[h];
     const int64_t oh = off[h];
     int tbits = 6;
-    while ((1 << tbits) < 2 * dh) ++tbits;
+    while ((1 << tbits) < spread * dh) ++tbits;
     const int32_t tsize = 1 << tbits;
     __syncthreads();
     if (threadIdx.x == 0) s_nlow = 0;
@@ -917,22 +929,23 @@ scan_status intersect_all(const IntersectConfig &cfg, int64_t n, int64_t nnz, co
   const hipStream_t ss = sh != s ? sh : sl;  // the small-owner events go on one of them
   SCAN_TRY(mark(stats ? stats->ev_small_begin : nullptr, ss));
   if (h.small || h.heavy) {
-    const size_t lds = small_lds_bytes(cfg.small_max);
-    if (lds > (size_t)lds_max) return fail(SCAN_EINVAL, "small_max too large for LDS");
-    if (lds > 65536) {
+    const int cap = std::min<int>(cfg.small_max, kLightDeg);  // light rows: LDS sized for them
+    const int spread1 = h.big ? kSpreadLight : kSpreadLightAlone;
+    const size_t lds = small_lds_bytes(cfg.small_max, kSpreadHeavy), lds1 = small_lds_bytes(cap, spread1);
+    if (lds > (size_t)lds_max || lds1 > (size_t)lds_max) return fail(SCAN_EINVAL, "small_max too large for LDS");
+    if (lds > 65536)
       SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<kSmallWaves>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (lds1 > 65536)
       SCAN_HIP_TRY(hipFuncSetAttribute((const void *)k_small_owner<1>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1));
     if (h.heavy)  // the longer rows first
       k_small_owner<kSmallWaves><<<h.heavy, kSmallWaves * kWave, lds, sh>>>(
-          heavy_list, &pc->heavy, nullptr, cfg.small_max, off, deg, adj, kind, sims, counts, cfg.skip_deg);
-    if (h.small) {
-      const int cap = std::min<int>(cfg.small_max, kLightDeg);  // light rows: LDS sized for them
-      k_small_owner<1><<<h.small, kWave, small_lds_bytes(cap), sl>>>(small_list, &pc->small, nullptr, cap, off,
-                                                                     deg, adj, kind, sims, counts, cfg.skip_deg);
-    }
+          heavy_list, &pc->heavy, nullptr, cfg.small_max, kSpreadHeavy, off, deg, adj, kind, sims, counts,
+          cfg.skip_deg);
+    if (h.small)
+      k_small_owner<1><<<h.small, kWave, lds1, sl>>>(small_list, &pc->small, nullptr, cap, spread1, off, deg, adj,
+                                                     kind, sims, counts, cfg.skip_deg);
     SCAN_HIP_TRY(hipGetLastError());
   }
   if (sl != ss) SCAN_TRY(stream_wait(ss, sl));  // the end event covers both
